@@ -1,0 +1,280 @@
+/*
+ * qg.h -- C ABI of the MI355X hot path of the Adam-based, reserve- and
+ * security-constrained AC unit-commitment solver (Chevalier, "A Parallelized,
+ * Adam-Based Solver for Reserve and Security Constrained AC Unit Commitment",
+ * PSCC 2024).
+ *
+ * One solver step is a forward and reverse pass of the penalised market-
+ * surplus objective (Section II-C, eq. (nlp_updated); gradient eq. (grads))
+ * over every period, bus, branch, generator and single-branch outage
+ * contingency (Section II-E), followed by the modified Adam update and the
+ * clip to the variable box (Section II-G, Alg. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Sizes: N buses, L branches, G generators, T periods, M cost blocks per
+ *   generator, K contingencies.
+ * - Host arrays are read during the call only and never retained.
+ * - Device buffers are allocated by the caller (the library never allocates
+ *   device memory); each must be 256-byte aligned.  The library keeps
+ *   non-owning pointers to the constant arena until qg_destroy_problem.
+ * - "stream" is a hipStream_t passed as void*; NULL means the default stream.
+ *   qg_eval_grad and qg_adam_step only enqueue work (no host synchronisation);
+ *   qg_build_problem and qg_solve synchronise the stream before returning.
+ * - The variable vector x (length n_x = 2TN + 4TG, FP64) holds six blocks in
+ *   this order, each period-major (entry (t, e) at t*E + e):
+ *     V  [T][N] voltage magnitudes      TH [T][N] voltage angles (rad)
+ *     P  [T][G] active output           Q  [T][G] reactive output
+ *     R  [T][G] spinning reserve        U  [T][G] relaxed on/off status
+ *   These are the basis variables of Section II-B (Omega_c, Omega_d) that
+ *   the reduced model keeps.
+ * - Every call returns a qg_status.  On error the outputs are left untouched
+ *   and qg_last_error() returns a description (thread-local).  No exception
+ *   or abort crosses the ABI.
+ */
+#ifndef QG_H
+#define QG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QG_OK = 0,
+  QG_ERR_ARG = 1,        /* bad size, index, value, null or misaligned pointer */
+  QG_ERR_TOPOLOGY = 2,   /* disconnected grid, or a listed outage that islands */
+  QG_ERR_SINGULAR = 3,   /* non-positive pivot in the susceptance factor */
+  QG_ERR_NONFINITE = 4,  /* NaN/Inf found where QG_FLAG_CHECK_FINITE asked */
+  QG_ERR_DEVICE = 5,     /* a HIP runtime call failed */
+  QG_ERR_STATE = 6       /* call out of order (e.g. destroyed handle) */
+} qg_status;
+
+/* Slots of the per-term objective vector (the families of Table 1's
+ * penalty breakdown, for the reduced model). */
+enum {
+  QG_T_DEV = 0,      /* block-bid energy, no-load, start-up/shut-down, reserve cost */
+  QG_T_BAL = 1,      /* power-balance soft-abs penalties (Example 4) */
+  QG_T_BR = 2,       /* branch thermal soft-ReLU penalties (Example 1) */
+  QG_T_ANG = 3,      /* branch angle-difference soft-ReLU penalties */
+  QG_T_PEN = 4,      /* penalised linear device constraints rho*sigma(Ax) */
+  QG_T_RSV = 5,      /* reserve shortfall */
+  QG_T_CTG_MAX = 6,  /* sum over periods of the worst contingency penalty */
+  QG_T_CTG_MEAN = 7, /* sum over periods of the mean contingency penalty */
+  QG_T_LOADVAL = 8,  /* consumer value (constant, enters with a minus sign) */
+  QG_T_TOTAL = 9,    /* the objective L = sum of slots 0..7 minus slot 8 */
+  QG_NTERMS = 10
+};
+
+/* Variable classes (the six blocks of x). */
+enum { QG_C_V = 0, QG_C_TH = 1, QG_C_P = 2, QG_C_Q = 3, QG_C_R = 4, QG_C_U = 5,
+       QG_NCLASS = 6 };
+
+enum { QG_CTG_ALL_NONBRIDGE = 0, QG_CTG_LIST = 1 };
+
+/* Flags for qg_build_opts.flags */
+#define QG_FLAG_CHECK_FINITE 0x1u /* qg_eval_grad rejects non-finite x (syncs) */
+
+/* Grid description: host arrays, all FP64 per unit (100 MVA base) unless
+ * stated; prices in $ per pu-hour, durations in hours. */
+typedef struct {
+  int32_t n_bus, n_branch, n_gen, n_period, n_seg;
+  /* branches [L]: endpoints, series r and x (x > 0, r >= 0), total line
+   * charging b_ch, base-case and contingency apparent-power ratings */
+  const int32_t *br_from, *br_to;
+  const double *br_r, *br_x, *br_bch, *br_smax, *br_smax_ctg;
+  /* generators [G] */
+  const int32_t *gen_bus;
+  const double *gen_pmin, *gen_pmax, *gen_qmin, *gen_qmax, *gen_rmax;
+  const double *gen_ru, *gen_rd;       /* ramp limits, pu per hour, when on */
+  const double *gen_ru_su, *gen_rd_sd; /* ramp allowance while starting/stopping */
+  const double *gen_p0, *gen_u0;       /* output and status before period 0 */
+  const double *gen_c_on, *gen_c_su, *gen_c_sd, *gen_c_r;
+  /* cost blocks [G*M], row-major per generator, marginal cost and size */
+  const double *gen_seg_cost, *gen_seg_size;
+  /* loads [T*N] period-major; reserve requirement and duration [T] */
+  const double *load_p, *load_q;
+  const double *reserve_req, *dt;
+  const double *v_min, *v_max;         /* [N] */
+  double c_p, c_q;     /* power-balance prices */
+  double c_s;          /* branch thermal (base and contingency) price */
+  double c_ang;        /* angle-difference price */
+  double ang_max;      /* angle-difference limit, rad */
+  double c_rsv;        /* reserve-shortfall price */
+  double rho;          /* penalty weight of the linear device constraints */
+  double load_value;   /* consumer value per pu-hour of load */
+} qg_grid_desc;
+
+typedef struct {
+  int32_t ref_bus;          /* reference bus of the reduced susceptance factor */
+  int32_t ctg_mode;         /* QG_CTG_ALL_NONBRIDGE or QG_CTG_LIST */
+  const int32_t *ctg_list;  /* [n_ctg] outaged branch per contingency (LIST) */
+  int32_t n_ctg;
+  uint32_t flags;
+} qg_build_opts;
+
+typedef struct {
+  size_t const_bytes;      /* device bytes of the constant arena */
+  size_t workspace_bytes;  /* device bytes of the per-call workspace */
+  int64_t n_x;             /* length of x */
+  int32_t n_ctg;           /* K actually used */
+} qg_sizes;
+
+typedef struct {
+  int64_t off[QG_NCLASS], len[QG_NCLASS];
+} qg_layout;
+
+/* Homotopy state of one evaluation (Section II-G): soft-function width eps,
+ * penalty scale beta and the multiplier of rho. */
+typedef struct {
+  double eps, beta, rho_scale;
+} qg_homotopy;
+
+typedef struct {
+  double beta1, beta2, eps;
+  int32_t eps_in_numerator; /* 1: the update printed in Alg. 3, (m_hat+eps)/(sqrt(v_hat)+eps) */
+} qg_adam_cfg;
+
+typedef struct {
+  int64_t n_steps;       /* Adam steps to run in this call */
+  int64_t iter0;         /* steps already taken (resume); first step is iter0+1 */
+  int64_t n_total;       /* schedule horizon tf; 0 means iter0 + n_steps */
+  int64_t check_every;   /* score check period (0: never) */
+  double alpha0[QG_NCLASS], alphaf[QG_NCLASS]; /* eqs. (norm_t)-(step_size) per class */
+  double eps0, epsf;     /* eps on the same reflected-sigmoid curve */
+  double beta0, betaf;   /* homotopy scale, linear in the iteration */
+  double rho0, rhof;     /* penalty multiplier, linear in the iteration */
+  double z_ed;           /* copper-plate bound (Proj. 3) for the gap stop; 0: none */
+  double stop_ratio;     /* stop once score / z_ed >= stop_ratio (if z_ed > 0) */
+  int32_t use_graph;     /* 1: replay captured HIP graphs; 0: plain launches */
+  int32_t profile;       /* 1: time each kernel with events (plain launches) */
+} qg_solve_opts;
+
+#define QG_NKERNELS 8
+typedef struct {
+  int64_t steps_done;
+  int64_t steps_to_gap;      /* first checked step with ratio >= stop_ratio, else -1 */
+  double wall_s;             /* host wall time of the call */
+  double time_to_gap_s;      /* wall time until steps_to_gap, else -1 */
+  double final_loss;         /* objective at the last schedule point */
+  double final_score;        /* -L at eps = 0, beta = 1, rho_scale = rhof */
+  double terms[QG_NTERMS];   /* score-point terms at the end */
+  double kernel_ms[QG_NKERNELS]; /* mean duration per launch when profile = 1 */
+  int64_t kernel_calls[QG_NKERNELS];
+} qg_solve_report;
+
+typedef struct qg_problem qg_problem;
+
+/*
+ * Sizes of the device buffers a problem needs.  Host-only: validates the
+ * description, finds the contingency set (non-islanding single-branch
+ * outages; Section II-E) and returns the arena and workspace sizes.
+ * Errors: ARG (sizes, indices, values), TOPOLOGY (disconnected grid, listed
+ * outage that islands).
+ */
+qg_status qg_problem_sizes(const qg_grid_desc* desc, const qg_build_opts* opts,
+                           qg_sizes* out);
+
+/*
+ * Build a problem: topology, contingency set, the FP64 factor of the reduced
+ * susceptance matrix (eq. (Yb_solve)), injection shift factors (the
+ * factor applied to unit injections, eq. (p_flow)) and line outage
+ * distribution factors (the rank-1 outage correction of eq. (rank_correct)
+ * expressed on flows); copies everything into d_const_arena (caller-owned,
+ * const_bytes long) on the given stream and synchronises it.
+ * Errors: ARG, TOPOLOGY, SINGULAR, DEVICE.  *out is set only on success.
+ */
+qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
+                           void* d_const_arena, size_t const_bytes, void* stream,
+                           qg_problem** out);
+
+/* Offsets and lengths of the six blocks of x. */
+qg_status qg_layout_of(const qg_problem* prob, qg_layout* out);
+
+/* Copy the contingency list actually used (K entries) into host memory. */
+qg_status qg_ctg_list(const qg_problem* prob, int32_t* out, int32_t capacity);
+
+/*
+ * Objective terms and gradient at x (Section II-C/II-E/II-F; gradient of
+ * eq. (grads) with every contingency included).
+ *   d_x         device [n_x], read only
+ *   d_grad      device [n_x] or NULL; receives dL/dx at x, including entries
+ *               at a bound (clipping happens only in Adam)
+ *   d_terms     device [QG_NTERMS] or NULL
+ *   h           host; eps >= 0, beta >= 0, rho_scale >= 0
+ *   d_workspace device, workspace_bytes long, caller-owned scratch
+ * Enqueued on the stream; no host synchronisation unless
+ * QG_FLAG_CHECK_FINITE was set at build.
+ */
+qg_status qg_eval_grad(qg_problem* prob, const double* d_x, double* d_grad,
+                       double* d_terms, const qg_homotopy* h, void* d_workspace,
+                       void* stream);
+
+/*
+ * One modified-Adam step with clip (Alg. 3) on device arrays of length n_x:
+ * m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
+ * x <- clip(x - lr_c (m/(1-b1^iter) [+eps]) / (sqrt(v/(1-b2^iter)) + eps)),
+ * with lr_c the step size of the entry's class and the clip to the box
+ * (v in [v_min, v_max], theta free, p in [0, pmax], q in [qmin, qmax],
+ * r in [0, rmax], u in [0, 1]).  iter is 1-based.
+ */
+qg_status qg_adam_step(qg_problem* prob, double* d_x, double* d_m, double* d_v,
+                       const double* d_grad, int64_t iter,
+                       const double lr[QG_NCLASS], const qg_adam_cfg* cfg,
+                       void* stream);
+
+/*
+ * Run n_steps of the Adam window of Alg. 4 (evaluate, backpropagate all
+ * contingencies, Adam, clip) with iteration-indexed schedules: step sizes
+ * per class and eps from eqs. (norm_t)-(step_size), beta and rho_scale
+ * linear.  x, m, v are updated in place (resume by passing iter0).  Every
+ * check_every steps the score -L(eps=0, beta=1, rho_scale=rhof) is read back
+ * for the gap stop against z_ed.  Synchronises the stream.
+ */
+qg_status qg_solve(qg_problem* prob, double* d_x, double* d_m, double* d_v,
+                   const qg_solve_opts* opts, const qg_adam_cfg* cfg,
+                   qg_solve_report* report, void* d_workspace, void* stream);
+
+/*
+ * Padded sizes and launch geometry, for tests and tools: dims[0..14] =
+ * N, L, G, T, M, K, Lp, Kp, Np, N4, Tp, nLb, nKb, ctg_bl, ctg_wl
+ * (Lp = L rounded up to 64, Kp = K up to 64, Np = N up to 16, N4 = N up to 4,
+ * Tp = T up to 16; nLb, nKb = partial-sum counts of the contingency
+ * map-reduce; ctg_bl, ctg_wl = its tile).  capacity must be >= 15.
+ */
+qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacity);
+
+/*
+ * Tile of the contingency map-reduce: bl branches per wavefront (8, 16 or 32)
+ * and wl wavefronts per block (1, 2, 4 or 8), with bl*wl >= 16.  The results
+ * do not depend on the tile except through the order of floating-point sums.
+ * Used by the autotuner.  Errors: ARG.
+ */
+qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl);
+
+/*
+ * Test support: copy an intermediate array of the last evaluation from the
+ * workspace into host memory (synchronises the stream).  Names and shapes
+ * (row-major, padded sizes from qg_problem_dims):
+ *   "F" [T][Lp] base-case DC flows      "Fk" [T][Kp] flows of outaged branches
+ *   "q2" [T][Lp] max(q_fr^2, q_to^2)    "pbarT" [N4][Tp] balanced injections
+ *   "lamp", "lamq" [T][N] balance multipliers
+ *   "zval" [T][Kp] contingency penalties z_tk
+ *   "gfT" [Lp][Tp] dL/dF                "gpb" [T][Np] dL/dp_bar before the
+ *   "qtot" [T][Lp] dL/d max(q^2)                       uniform-slack correction
+ *   "params" [16] step parameter block  "terms" [QG_NTERMS]
+ * bytes must not exceed the array's size.  Errors: ARG, DEVICE.
+ */
+qg_status qg_debug_fetch(const qg_problem* prob, const void* d_workspace, const char* name,
+                         void* host, size_t bytes, void* stream);
+
+void qg_destroy_problem(qg_problem* prob);
+const char* qg_status_string(qg_status s);
+const char* qg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QG_H */

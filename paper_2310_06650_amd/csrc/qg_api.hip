@@ -1,0 +1,400 @@
+// extern "C" entry points of qg.h: argument checks, uploads, stream handling,
+// graph capture of the solve loop and error plumbing.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "qg_internal.h"
+
+namespace qg {
+const char* last_error_text();
+}
+
+struct qg_problem {
+  qg::Problem p;
+  hipStream_t own = nullptr;  // non-blocking stream for capture when the caller passes NULL
+  bool alive = true;
+};
+
+namespace {
+
+using qg::fail;
+
+bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % qg::kAlign) == 0; }
+
+qg_status hip_fail(hipError_t e, const char* what) {
+  return fail(QG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                   \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+qg_status check_problem(const qg_problem* pr) {
+  if (!pr) return fail(QG_ERR_ARG, "null problem handle");
+  if (!pr->alive) return fail(QG_ERR_STATE, "problem handle already destroyed");
+  return QG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qg_status_string(qg_status s) {
+  switch (s) {
+    case QG_OK: return "ok";
+    case QG_ERR_ARG: return "invalid argument";
+    case QG_ERR_TOPOLOGY: return "topology error";
+    case QG_ERR_SINGULAR: return "singular susceptance matrix";
+    case QG_ERR_NONFINITE: return "non-finite input";
+    case QG_ERR_DEVICE: return "device error";
+    case QG_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* qg_last_error(void) { return qg::last_error_text(); }
+
+qg_status qg_problem_sizes(const qg_grid_desc* desc, const qg_build_opts* opts, qg_sizes* out) {
+  if (!out) return fail(QG_ERR_ARG, "null output");
+  qg::Problem p;
+  qg_status s = qg::plan_problem(desc, opts, &p);
+  if (s != QG_OK) return s;
+  out->const_bytes = p.const_bytes;
+  out->workspace_bytes = p.work_bytes;
+  out->n_x = p.n_x;
+  out->n_ctg = p.K;
+  return QG_OK;
+}
+
+qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
+                           void* d_const_arena, size_t const_bytes, void* stream,
+                           qg_problem** out) {
+  if (!out) return fail(QG_ERR_ARG, "null output handle");
+  if (!d_const_arena || !aligned(d_const_arena))
+    return fail(QG_ERR_ARG, "constant arena must be non-null and 256-byte aligned");
+  qg_problem* pr = new (std::nothrow) qg_problem();
+  if (!pr) return fail(QG_ERR_ARG, "host allocation failed");
+  qg_status s = qg::plan_problem(desc, opts, &pr->p);
+  if (s != QG_OK) { delete pr; return s; }
+  if (const_bytes < pr->p.const_bytes) {
+    delete pr;
+    return fail(QG_ERR_ARG, "constant arena too small: need " + std::to_string(pr->p.const_bytes));
+  }
+  qg::HostBuild hb;
+  s = qg::build_arena(desc, opts, &pr->p, &hb);
+  if (s != QG_OK) { delete pr; return s; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(d_const_arena, hb.image.data(), hb.image.size(),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pr->own, hipStreamNonBlocking);
+  if (e != hipSuccess) { delete pr; return hip_fail(e, "upload of the constant arena"); }
+  qg::rebase_pointers(&pr->p, d_const_arena);
+  *out = pr;
+  return QG_OK;
+}
+
+qg_status qg_layout_of(const qg_problem* pr, qg_layout* out) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!out) return fail(QG_ERR_ARG, "null output");
+  const int64_t TN = (int64_t)pr->p.T * pr->p.N, TG = (int64_t)pr->p.T * pr->p.G;
+  const int64_t len[QG_NCLASS] = {TN, TN, TG, TG, TG, TG};
+  int64_t o = 0;
+  for (int c = 0; c < QG_NCLASS; ++c) { out->off[c] = o; out->len[c] = len[c]; o += len[c]; }
+  return QG_OK;
+}
+
+qg_status qg_ctg_list(const qg_problem* pr, int32_t* out, int32_t capacity) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (capacity < pr->p.K || (pr->p.K > 0 && !out)) return fail(QG_ERR_ARG, "output too small");
+  for (int k = 0; k < pr->p.K; ++k) out[k] = pr->p.ctg[k];
+  return QG_OK;
+}
+
+qg_status qg_problem_dims(const qg_problem* pr, int32_t* d, int32_t capacity) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d || capacity < 15) return fail(QG_ERR_ARG, "dims needs 15 entries");
+  const qg::Problem& p = pr->p;
+  const int32_t v[15] = {p.N, p.L, p.G, p.T, p.M, p.K, p.Lp, p.Kp, p.Np, p.N4, p.Tp,
+                         p.nLb, p.nKb, p.tile.bl, p.tile.wl};
+  std::memcpy(d, v, sizeof(v));
+  return QG_OK;
+}
+
+qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!(bl == 8 || bl == 16 || bl == 32) || !(wl == 1 || wl == 2 || wl == 4 || wl == 8) ||
+      bl * wl < 16)
+    return fail(QG_ERR_ARG, "tile must have bl in {8,16,32}, wl in {1,2,4,8}, bl*wl >= 16");
+  qg::Problem& p = pr->p;
+  p.tile = qg::CtgTile{bl, wl};
+  const int span = bl * wl;
+  p.nLb = (p.Lp + span - 1) / span;
+  return QG_OK;
+}
+
+qg_status qg_eval_grad(qg_problem* pr, const double* d_x, double* d_grad, double* d_terms,
+                       const qg_homotopy* h, void* d_workspace, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d_x || !h || !d_workspace) return fail(QG_ERR_ARG, "null x, homotopy or workspace");
+  if (!aligned(d_x) || !aligned(d_workspace) || (d_grad && !aligned(d_grad)) ||
+      (d_terms && !aligned(d_terms)))
+    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+  if (!(h->eps >= 0.0) || !(h->beta >= 0.0) || !(h->rho_scale >= 0.0) || !std::isfinite(h->eps) ||
+      !std::isfinite(h->beta) || !std::isfinite(h->rho_scale))
+    return fail(QG_ERR_ARG, "homotopy values must be finite and non-negative");
+  const qg::Problem& p = pr->p;
+  qg::DevWork w = qg::carve_workspace(&p, d_workspace);
+  if (p.flags & QG_FLAG_CHECK_FINITE) {
+    int* flag = reinterpret_cast<int*>(w.params + 14);
+    if (qg::launch_check_finite(&p, d_x, flag, stream) != 0)
+      return hip_fail(hipGetLastError(), "finite check launch");
+    int hflag = 0;
+    HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost,
+                           static_cast<hipStream_t>(stream)), "finite check read");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "finite check sync");
+    if (hflag) return fail(QG_ERR_NONFINITE, "x holds a NaN or Inf");
+  }
+  qg::EvalMode m{};
+  m.schedule = 0;
+  m.eps = h->eps;
+  m.beta = h->beta;
+  m.rho_s = h->rho_scale;
+  int e = qg::launch_eval(&p, w, d_x, d_grad, d_terms, m, 0, nullptr, nullptr, stream, nullptr);
+  if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+  return QG_OK;
+}
+
+qg_status qg_adam_step(qg_problem* pr, double* d_x, double* d_m, double* d_v,
+                       const double* d_grad, int64_t iter, const double lr[QG_NCLASS],
+                       const qg_adam_cfg* cfg, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d_x || !d_m || !d_v || !d_grad || !lr || !cfg)
+    return fail(QG_ERR_ARG, "null argument");
+  if (!aligned(d_x) || !aligned(d_m) || !aligned(d_v) || !aligned(d_grad))
+    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+  if (iter < 1) return fail(QG_ERR_ARG, "iter is 1-based");
+  if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
+      !(cfg->eps > 0.0))
+    return fail(QG_ERR_ARG, "need 0 <= beta1, beta2 < 1 and eps > 0");
+  const double bc1 = 1.0 - std::pow(cfg->beta1, (double)iter);
+  const double bc2 = 1.0 - std::pow(cfg->beta2, (double)iter);
+  int e = qg::launch_adam(&pr->p, d_x, d_m, d_v, d_grad, lr, bc1, bc2, cfg->beta1, cfg->beta2,
+                          cfg->eps, cfg->eps_in_numerator, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+  return QG_OK;
+}
+
+qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
+                   const qg_solve_opts* o, const qg_adam_cfg* cfg, qg_solve_report* rep,
+                   void* d_workspace, void* stream) {
+  using clock = std::chrono::steady_clock;
+  const auto t_start = clock::now();
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d_x || !d_m || !d_v || !o || !cfg || !rep || !d_workspace)
+    return fail(QG_ERR_ARG, "null argument");
+  if (!aligned(d_x) || !aligned(d_m) || !aligned(d_v) || !aligned(d_workspace))
+    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+  if (o->n_steps < 0 || o->iter0 < 0 || o->check_every < 0)
+    return fail(QG_ERR_ARG, "negative step counts");
+  const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
+  if (o->iter0 + o->n_steps > n_total) return fail(QG_ERR_ARG, "n_total below iter0 + n_steps");
+  for (int c = 0; c < QG_NCLASS; ++c)
+    if (!(o->alpha0[c] > 0.0) || !(o->alphaf[c] > 0.0))
+      return fail(QG_ERR_ARG, "step sizes must be positive");
+  if (!(o->eps0 > 0.0) || !(o->epsf > 0.0)) return fail(QG_ERR_ARG, "eps0, epsf must be positive");
+  if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
+      !(cfg->eps > 0.0))
+    return fail(QG_ERR_ARG, "need 0 <= beta1, beta2 < 1 and eps > 0");
+
+  const qg::Problem& p = pr->p;
+  qg::DevWork w = qg::carve_workspace(&p, d_workspace);
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  hipStream_t ex = user ? user : pr->own;
+  if (!user) {
+    // order the internal stream after prior work on the default stream
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+    HIP_TRY(hipEventRecord(ev, nullptr), "event record");
+    HIP_TRY(hipStreamWaitEvent(ex, ev, 0), "stream wait");
+    (void)hipEventDestroy(ev);
+  }
+
+  qg::EvalMode sm;
+  std::memset(&sm, 0, sizeof(sm));  // memcmp below compares padding too
+  sm.schedule = 1;
+  sm.n_total = n_total;
+  for (int c = 0; c < QG_NCLASS; ++c) { sm.alpha0[c] = o->alpha0[c]; sm.alphaf[c] = o->alphaf[c]; }
+  sm.eps0 = o->eps0; sm.epsf = o->epsf;
+  sm.beta0 = o->beta0; sm.betaf = o->betaf;
+  sm.rho0 = o->rho0; sm.rhof = o->rhof;
+  sm.adam_b1 = cfg->beta1; sm.adam_b2 = cfg->beta2; sm.adam_eps = cfg->eps;
+  sm.eps_in_num = cfg->eps_in_numerator;
+
+  qg::EvalMode score{};
+  score.schedule = 0;
+  score.eps = 0.0;
+  score.beta = 1.0;
+  score.rho_s = o->rhof;
+
+  std::memset(rep, 0, sizeof(*rep));
+  rep->steps_to_gap = -1;
+  rep->time_to_gap_s = -1.0;
+
+  if (qg::launch_set_step(&p, w, o->iter0, ex) != 0) return hip_fail(hipGetLastError(), "launch");
+
+  const bool profile = o->profile != 0;
+  const bool graph = o->use_graph != 0 && !profile;
+  hipEvent_t evs[QG_NKERNELS];
+  if (profile)
+    for (int i = 0; i < 7; ++i) HIP_TRY(hipEventCreate(&evs[i]), "event");
+
+  // graph of gsteps consecutive steps (the step counter lives on the device)
+  const int gsteps = 8;
+  hipGraphExec_t gexec = static_cast<hipGraphExec_t>(pr->p.graph_exec);
+  if (graph && o->n_steps >= gsteps) {
+    const void* key[5] = {d_x, d_m, d_v, d_workspace, nullptr};
+    bool hit = gexec && std::memcmp(key, pr->p.graph_key, sizeof(key)) == 0 &&
+               pr->p.graph_steps == gsteps;
+    // the schedule constants are kernel arguments, so a different schedule
+    // needs a new capture as well
+    if (hit && std::memcmp(&pr->p.graph_mode, &sm, sizeof(sm)) != 0) hit = false;
+    if (!hit) {
+      if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; pr->p.graph_exec = nullptr; }
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(pr->own, hipStreamCaptureModeThreadLocal), "begin capture");
+      for (int k = 0; k < gsteps; ++k)
+        qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, pr->own, nullptr);
+      HIP_TRY(hipStreamEndCapture(pr->own, &g), "end capture");
+      hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+      pr->p.graph_exec = gexec;
+      std::memcpy(pr->p.graph_key, key, sizeof(key));
+      pr->p.graph_steps = gsteps;
+      std::memcpy(&pr->p.graph_mode, &sm, sizeof(sm));
+    }
+  }
+
+  auto run_steps = [&](int64_t n) -> qg_status {
+    int64_t left = n;
+    if (graph && gexec) {
+      while (left >= gsteps) {
+        HIP_TRY(hipGraphLaunch(gexec, ex), "graph launch");
+        left -= gsteps;
+      }
+    }
+    for (int64_t k = 0; k < left; ++k) {
+      int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, ex,
+                              profile ? reinterpret_cast<void**>(evs) : nullptr);
+      if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+      if (profile) {
+        HIP_TRY(hipEventSynchronize(evs[6]), "event sync");
+        for (int q = 0; q < 6; ++q) {
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, evs[q], evs[q + 1]), "elapsed");
+          rep->kernel_ms[q] += ms;
+          rep->kernel_calls[q] += 1;
+        }
+      }
+    }
+    return QG_OK;
+  };
+
+  auto eval_score = [&](double* total, double* terms) -> qg_status {
+    int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, score, 0, nullptr, nullptr, ex, nullptr);
+    if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+    HIP_TRY(hipMemcpyAsync(terms, w.terms, QG_NTERMS * sizeof(double), hipMemcpyDeviceToHost, ex),
+            "terms read");
+    HIP_TRY(hipStreamSynchronize(ex), "sync");
+    *total = terms[QG_T_TOTAL];
+    return QG_OK;
+  };
+
+  int64_t done = 0;
+  while (done < o->n_steps) {
+    int64_t n = o->n_steps - done;
+    if (o->check_every > 0) n = std::min(n, o->check_every - (done % o->check_every));
+    s = run_steps(n);
+    if (s != QG_OK) return s;
+    done += n;
+    if (o->check_every > 0 && (done % o->check_every == 0) && o->z_ed > 0.0) {
+      double tot, terms[QG_NTERMS];
+      s = eval_score(&tot, terms);
+      if (s != QG_OK) return s;
+      const double ratio = -tot / o->z_ed;
+      if (ratio >= o->stop_ratio) {
+        rep->steps_to_gap = done;
+        rep->time_to_gap_s = std::chrono::duration<double>(clock::now() - t_start).count();
+        break;
+      }
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(ex), "sync");
+  rep->steps_done = done;
+  rep->wall_s = std::chrono::duration<double>(clock::now() - t_start).count();
+  // objective at the last schedule point was left in the workspace terms
+  double last[QG_NTERMS];
+  HIP_TRY(hipMemcpy(last, w.terms, sizeof(last), hipMemcpyDeviceToHost), "terms read");
+  rep->final_loss = last[QG_T_TOTAL];
+  double tot;
+  s = eval_score(&tot, rep->terms);
+  if (s != QG_OK) return s;
+  rep->final_score = -tot;
+  if (profile) {
+    for (int q = 0; q < 6; ++q)
+      if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
+    for (int i = 0; i < 7; ++i) (void)hipEventDestroy(evs[i]);
+  }
+  return QG_OK;
+}
+
+qg_status qg_debug_fetch(const qg_problem* pr, const void* d_workspace, const char* name,
+                         void* host, size_t bytes, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d_workspace || !name || !host) return fail(QG_ERR_ARG, "null argument");
+  const qg::Problem& p = pr->p;
+  qg::DevWork w = qg::carve_workspace(&p, const_cast<void*>(d_workspace));
+  const size_t D = sizeof(double);
+  struct Item { const char* n; const void* ptr; size_t bytes; };
+  const Item items[] = {
+      {"F", w.F, (size_t)p.T * p.Lp * D},       {"Fk", w.Fk, (size_t)p.T * p.Kp * D},
+      {"q2", w.q2, (size_t)p.T * p.Lp * D},     {"pbarT", w.pbarT, (size_t)p.N4 * p.Tp * D},
+      {"lamp", w.lamp, (size_t)p.T * p.N * D},  {"lamq", w.lamq, (size_t)p.T * p.N * D},
+      {"zval", w.zval, (size_t)p.T * p.Kp * D}, {"gfT", w.gfT, (size_t)p.Lp * p.Tp * D},
+      {"gpb", w.gpb, (size_t)p.T * p.Np * D},   {"qtot", w.qtot, (size_t)p.T * p.Lp * D},
+      {"params", w.params, (size_t)qg::kParams * D}, {"terms", w.terms, (size_t)QG_NTERMS * D}};
+  for (const Item& it : items) {
+    if (std::strcmp(it.n, name) != 0) continue;
+    if (bytes > it.bytes) return fail(QG_ERR_ARG, "request larger than the array");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(host, it.ptr, bytes, hipMemcpyDeviceToHost, st), "debug copy");
+    HIP_TRY(hipStreamSynchronize(st), "sync");
+    return QG_OK;
+  }
+  return fail(QG_ERR_ARG, std::string("unknown array ") + name);
+}
+
+void qg_destroy_problem(qg_problem* pr) {
+  if (!pr) return;
+  if (pr->p.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(pr->p.graph_exec));
+  if (pr->own) (void)hipStreamDestroy(pr->own);
+  pr->alive = false;
+  delete pr;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal types shared by the host builder, the kernels and the C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qg.h"
+
+namespace qg {
+
+constexpr int kAlign = 256;
+constexpr int kMaxT = 64;          // periods per problem (4 MFMA row tiles of 16)
+constexpr int kBlock = 256;        // threads per block of the streaming kernels
+constexpr int kCtgLanes = 64;      // contingencies per wavefront in the map-reduce
+constexpr int kParams = 16;        // doubles in the per-step parameter block
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Device view of the constant arena (all pointers into caller memory).
+struct DevProblem {
+  int N, L, G, T, M, K;
+  int Lp;    // L padded to 64 (row count of the outage-factor tile space)
+  int Kp;    // K padded to 64 (one wavefront of contingencies)
+  int Np;    // N padded to 16 (MFMA output columns of the adjoint product)
+  int N4;    // N padded to 4  (MFMA reduction depth of the flow product)
+  int Tp;    // T padded to 16 (MFMA rows)
+  int twoL;  // endpoint slots per period
+  // branches
+  const int* br_from; const int* br_to; const int* slot_fr; const int* slot_to;
+  const double* br_g; const double* br_b; const double* br_bh; const double* br_smax;
+  const double* ctg_smax;   // [Lp] contingency rating (1 on padding)
+  const double* ctg_smax2;  // [Lp] its square
+  const int* kof;           // [Lp] contingency index of a branch, -1 if none
+  const int* brk;           // [Kp] outaged branch of a contingency (0 on padding)
+  // buses
+  const int* bptr;          // [N+1] endpoint-slot ranges (bus-sorted)
+  const int* gptr;          // [N+1] generator ranges
+  const int* glist;         // [G]   generators sorted by bus
+  const double* vmin; const double* vmax;
+  // generators
+  const int* gen_bus;
+  const double *pmin, *pmax, *qmin, *qmax, *rmax, *ru, *rd, *rusu, *rdsd, *p0, *u0;
+  const double *con, *csu, *csd, *cr;
+  const double *seg_cost, *seg_size, *pcum;   // [G*M]
+  // periods
+  const double* load_p; const double* load_q;  // [T*N]
+  const double* dt; const double* rsv_req; const double* sum_load;  // [T]
+  // sensitivities
+  const double* isft;   // [N4][Lp]   ISF transposed, zero padded
+  const double* isf;    // [Lp][Np]   ISF, zero padded
+  const double* lodf;   // [Lp][Kp]   outage factors; NaN marks (k,k) and padding
+  // prices
+  double c_p, c_q, c_s, c_ang, ang_max, c_rsv, rho, vload;
+};
+
+// Device view of the caller's workspace.
+struct DevWork {
+  double* params;      // [kParams]
+  int64_t* step;       // [1] Adam iteration counter used by qg_solve
+  double* epP; double* epQ;      // [T][2L] branch flows at bus-sorted endpoint slots
+  double* bco;         // [9][T][L] per-branch reverse coefficients
+  double* q2;          // [T][Lp]  max(q_fr^2, q_to^2)
+  double* pbarT;       // [N4][Tp] balanced injections, transposed
+  double* F;           // [T][Lp]  base-case DC flows
+  double* Fk;          // [T][Kp]  flows of the outaged branches
+  double* lamp; double* lamq;    // [T][N] balance multipliers
+  double* gdev;        // [4][T][G] device-only partials of p, q, r, u
+  double* zpart; double* spart;  // [nLb][T][Kp]
+  double* rpart; double* qpart;  // [nKb][T][Lp]
+  double* smean;       // [T][Kp]
+  double* zval;        // [T][Kp]
+  double* gfT;         // [Lp][Tp] dL/dF, transposed
+  double* qtot;        // [T][Lp]  dL/d qmax2
+  double* gpb;         // [T][Np]  dL/d p_bar
+  double* epGV; double* epGT;    // [T][2L] endpoint adjoints
+  double* tpart;       // term partial sums
+  double* terms;       // [QG_NTERMS] last evaluated terms
+  double* grad;        // [n_x] gradient scratch for qg_solve's eager path
+};
+
+// Offsets of the term partial sums inside DevWork::tpart.
+struct TermOffsets {
+  int br, ang, dev, pen, rsv, bal, cmax, cmean, total;
+};
+
+// Tile shape of the contingency map-reduce.
+struct CtgTile {
+  int bl;   // branches per wavefront (8, 16 or 32)
+  int wl;   // wavefronts per block, stacked along branches
+};
+
+// Homotopy source of one evaluation.
+struct EvalMode {
+  int schedule;          // 0: homotopy from args, 1: from the solve schedule
+  double eps, beta, rho_s;
+  // schedule (mode 1)
+  int64_t n_total;
+  double alpha0[QG_NCLASS], alphaf[QG_NCLASS];
+  double eps0, epsf, beta0, betaf, rho0, rhof;
+  double adam_b1, adam_b2, adam_eps;
+  int eps_in_num;
+};
+
+struct Problem {
+  // sizes
+  int N, L, G, T, M, K;
+  int Lp, Kp, Np, N4, Tp;
+  int64_t n_x;
+  uint32_t flags;
+  std::vector<int32_t> ctg;
+  // launch geometry
+  int nb_br;      // blocks of the per-(t, branch) kernels
+  int nb_bus;     // blocks of the per-(t, bus chunk) kernels
+  int bus_chunks; // bus chunks per period
+  CtgTile tile;
+  int nLb, nKb;   // partial counts of the contingency map-reduce
+  int nLb_max, nKb_max;
+  TermOffsets toff;
+  size_t const_bytes, work_bytes;
+  DevProblem dp;
+  void* arena = nullptr;
+  // graph cache of qg_solve
+  void* graph_exec = nullptr;
+  const void* graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int graph_steps = 0;
+  EvalMode graph_mode{};
+};
+
+// Host build products (before upload).
+struct HostBuild {
+  std::vector<unsigned char> image;  // arena image
+  size_t const_bytes = 0;
+};
+
+// Set the thread-local error text; returns s.
+qg_status fail(qg_status s, const std::string& msg);
+
+// Validate the description and find the contingency set.  Fills p's sizes.
+qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p);
+// Factor, sensitivities and the arena image; sets offsets in p->dp relative
+// to arena base (as byte offsets cast to pointers) -- rebased on upload.
+qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
+                      HostBuild* hb);
+void rebase_pointers(Problem* p, void* arena);
+DevWork carve_workspace(const Problem* p, void* ws);
+
+
+
+// Kernel launchers (qg_kernels.hip).
+int launch_eval(const Problem* p, const DevWork& w, const double* x, double* grad,
+                double* terms_out, const EvalMode& mode, int fuse_adam, double* m,
+                double* v, void* stream, void** events /* nullable [2*QG_NKERNELS] */);
+int launch_adam(const Problem* p, double* x, double* m, double* v, const double* g,
+                const double lr[QG_NCLASS], double bc1, double bc2, double b1,
+                double b2, double eps, int eps_in_num, void* stream);
+int launch_set_step(const Problem* p, const DevWork& w, int64_t value, void* stream);
+int launch_check_finite(const Problem* p, const double* x, int* flag, void* stream);
+
+}  // namespace qg

@@ -1,0 +1,370 @@
+"""ctypes binding of the qg C ABI (include/qg.h).
+
+The functions named like the C entry points only marshal arguments and raise
+QgError on a non-OK status; every step of the hot path runs in the HIP library
+libqg.so, which must be built (``python -m paper_2310_06650_amd.build``).
+There is no fallback: importing this module without the library fails.
+
+``Problem`` is a convenience owner of the device buffers (torch tensors) of one
+problem.  PyTorch only provides device memory and streams here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -m paper_2310_06650_amd.build)")
+lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants
+QG_OK, QG_ERR_ARG, QG_ERR_TOPOLOGY, QG_ERR_SINGULAR, QG_ERR_NONFINITE, \
+    QG_ERR_DEVICE, QG_ERR_STATE = range(7)
+TERM_NAMES = ("dev", "bal", "br", "ang", "pen", "rsv", "ctg_max", "ctg_mean",
+              "load_value", "total")
+QG_NTERMS = 10
+QG_NCLASS = 6
+QG_NKERNELS = 8
+QG_CTG_ALL_NONBRIDGE, QG_CTG_LIST = 0, 1
+QG_FLAG_CHECK_FINITE = 0x1
+KERNEL_NAMES = ("k_forward", "k_balance_flow", "k_ctg_main", "k_ctg_finalize",
+                "k_adjoint", "k_final")
+
+_pd = C.POINTER(C.c_double)
+_pi = C.POINTER(C.c_int32)
+
+
+class qg_grid_desc(C.Structure):
+    _fields_ = [
+        ("n_bus", C.c_int32), ("n_branch", C.c_int32), ("n_gen", C.c_int32),
+        ("n_period", C.c_int32), ("n_seg", C.c_int32),
+        ("br_from", _pi), ("br_to", _pi),
+        ("br_r", _pd), ("br_x", _pd), ("br_bch", _pd), ("br_smax", _pd), ("br_smax_ctg", _pd),
+        ("gen_bus", _pi),
+        ("gen_pmin", _pd), ("gen_pmax", _pd), ("gen_qmin", _pd), ("gen_qmax", _pd),
+        ("gen_rmax", _pd), ("gen_ru", _pd), ("gen_rd", _pd), ("gen_ru_su", _pd),
+        ("gen_rd_sd", _pd), ("gen_p0", _pd), ("gen_u0", _pd), ("gen_c_on", _pd),
+        ("gen_c_su", _pd), ("gen_c_sd", _pd), ("gen_c_r", _pd),
+        ("gen_seg_cost", _pd), ("gen_seg_size", _pd),
+        ("load_p", _pd), ("load_q", _pd), ("reserve_req", _pd), ("dt", _pd),
+        ("v_min", _pd), ("v_max", _pd),
+        ("c_p", C.c_double), ("c_q", C.c_double), ("c_s", C.c_double),
+        ("c_ang", C.c_double), ("ang_max", C.c_double), ("c_rsv", C.c_double),
+        ("rho", C.c_double), ("load_value", C.c_double)]
+
+
+class qg_build_opts(C.Structure):
+    _fields_ = [("ref_bus", C.c_int32), ("ctg_mode", C.c_int32), ("ctg_list", _pi),
+                ("n_ctg", C.c_int32), ("flags", C.c_uint32)]
+
+
+class qg_sizes(C.Structure):
+    _fields_ = [("const_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
+                ("n_x", C.c_int64), ("n_ctg", C.c_int32)]
+
+
+class qg_layout(C.Structure):
+    _fields_ = [("off", C.c_int64 * QG_NCLASS), ("len", C.c_int64 * QG_NCLASS)]
+
+
+class qg_homotopy(C.Structure):
+    _fields_ = [("eps", C.c_double), ("beta", C.c_double), ("rho_scale", C.c_double)]
+
+
+class qg_adam_cfg(C.Structure):
+    _fields_ = [("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("eps_in_numerator", C.c_int32)]
+
+
+class qg_solve_opts(C.Structure):
+    _fields_ = [("n_steps", C.c_int64), ("iter0", C.c_int64), ("n_total", C.c_int64),
+                ("check_every", C.c_int64),
+                ("alpha0", C.c_double * QG_NCLASS), ("alphaf", C.c_double * QG_NCLASS),
+                ("eps0", C.c_double), ("epsf", C.c_double), ("beta0", C.c_double),
+                ("betaf", C.c_double), ("rho0", C.c_double), ("rhof", C.c_double),
+                ("z_ed", C.c_double), ("stop_ratio", C.c_double),
+                ("use_graph", C.c_int32), ("profile", C.c_int32)]
+
+
+class qg_solve_report(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("steps_to_gap", C.c_int64),
+                ("wall_s", C.c_double), ("time_to_gap_s", C.c_double),
+                ("final_loss", C.c_double), ("final_score", C.c_double),
+                ("terms", C.c_double * QG_NTERMS),
+                ("kernel_ms", C.c_double * QG_NKERNELS),
+                ("kernel_calls", C.c_int64 * QG_NKERNELS)]
+
+
+_vp = C.c_void_p
+_sig = {
+    "qg_problem_sizes": (C.c_int, [C.POINTER(qg_grid_desc), C.POINTER(qg_build_opts),
+                                   C.POINTER(qg_sizes)]),
+    "qg_build_problem": (C.c_int, [C.POINTER(qg_grid_desc), C.POINTER(qg_build_opts), _vp,
+                                   C.c_size_t, _vp, C.POINTER(_vp)]),
+    "qg_layout_of": (C.c_int, [_vp, C.POINTER(qg_layout)]),
+    "qg_ctg_list": (C.c_int, [_vp, _pi, C.c_int32]),
+    "qg_problem_dims": (C.c_int, [_vp, _pi, C.c_int32]),
+    "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "qg_eval_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp, _vp]),
+    "qg_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double * QG_NCLASS,
+                               C.POINTER(qg_adam_cfg), _vp]),
+    "qg_solve": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_solve_opts),
+                           C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp, _vp]),
+    "qg_debug_fetch": (C.c_int, [_vp, _vp, C.c_char_p, _vp, C.c_size_t, _vp]),
+    "qg_destroy_problem": (None, [_vp]),
+    "qg_status_string": (C.c_char_p, [C.c_int]),
+    "qg_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class QgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        detail = lib.qg_last_error().decode()
+        super().__init__(f"{where}: {lib.qg_status_string(status).decode()} ({status}): {detail}")
+
+
+def _check(status, where):
+    if status != QG_OK:
+        raise QgError(status, where)
+
+
+# ---------------------------------------------------------------- marshalling
+
+def grid_desc(case):
+    """qg_grid_desc for a GridCase; returns (desc, keepalive)."""
+    keep = []
+
+    def d(a):
+        arr = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(arr)
+        return arr.ctypes.data_as(_pd)
+
+    def i(a):
+        arr = np.ascontiguousarray(a, dtype=np.int32)
+        keep.append(arr)
+        return arr.ctypes.data_as(_pi)
+
+    c = case
+    desc = qg_grid_desc(
+        n_bus=c.n_bus, n_branch=c.n_branch, n_gen=c.n_gen, n_period=c.n_period,
+        n_seg=c.n_seg, br_from=i(c.br_from), br_to=i(c.br_to), br_r=d(c.br_r),
+        br_x=d(c.br_x), br_bch=d(c.br_bch), br_smax=d(c.br_smax),
+        br_smax_ctg=d(c.br_smax_ctg), gen_bus=i(c.gen_bus), gen_pmin=d(c.gen_pmin),
+        gen_pmax=d(c.gen_pmax), gen_qmin=d(c.gen_qmin), gen_qmax=d(c.gen_qmax),
+        gen_rmax=d(c.gen_rmax), gen_ru=d(c.gen_ru), gen_rd=d(c.gen_rd),
+        gen_ru_su=d(c.gen_ru_su), gen_rd_sd=d(c.gen_rd_sd), gen_p0=d(c.gen_p0),
+        gen_u0=d(c.gen_u0), gen_c_on=d(c.gen_c_on), gen_c_su=d(c.gen_c_su),
+        gen_c_sd=d(c.gen_c_sd), gen_c_r=d(c.gen_c_r), gen_seg_cost=d(c.gen_seg_cost),
+        gen_seg_size=d(c.gen_seg_size), load_p=d(c.load_p), load_q=d(c.load_q),
+        reserve_req=d(c.reserve_req), dt=d(c.dt), v_min=d(c.v_min), v_max=d(c.v_max),
+        c_p=c.c_p, c_q=c.c_q, c_s=c.c_s, c_ang=c.c_ang, ang_max=c.ang_max,
+        c_rsv=c.c_rsv, rho=c.rho, load_value=c.load_value)
+    return desc, keep
+
+
+def build_opts(case=None, ctg_mode=QG_CTG_LIST, ctg_list=None, ref_bus=None, flags=0):
+    keep = []
+    if ctg_list is None and case is not None and ctg_mode == QG_CTG_LIST:
+        ctg_list = case.ctg_list
+    ptr = None
+    n = 0
+    if ctg_list is not None:
+        arr = np.ascontiguousarray(ctg_list, dtype=np.int32)
+        keep.append(arr)
+        ptr = arr.ctypes.data_as(_pi)
+        n = int(arr.shape[0])
+    if ref_bus is None:
+        ref_bus = case.ref_bus if case is not None else 0
+    return qg_build_opts(ref_bus=ref_bus, ctg_mode=ctg_mode, ctg_list=ptr, n_ctg=n,
+                         flags=flags), keep
+
+
+# ---------------------------------------------------------------- C-named calls
+
+def qg_problem_sizes(desc, opts):
+    out = qg_sizes()
+    _check(lib.qg_problem_sizes(C.byref(desc), C.byref(opts), C.byref(out)), "qg_problem_sizes")
+    return out
+
+
+def qg_build_problem(desc, opts, d_arena, const_bytes, stream):
+    h = _vp()
+    _check(lib.qg_build_problem(C.byref(desc), C.byref(opts), d_arena, const_bytes, stream,
+                                C.byref(h)), "qg_build_problem")
+    return h
+
+
+def qg_layout_of(h):
+    out = qg_layout()
+    _check(lib.qg_layout_of(h, C.byref(out)), "qg_layout_of")
+    return out
+
+
+def qg_ctg_list(h, k):
+    out = np.zeros(max(k, 1), dtype=np.int32)
+    _check(lib.qg_ctg_list(h, out.ctypes.data_as(_pi), out.shape[0]), "qg_ctg_list")
+    return out[:k]
+
+
+def qg_problem_dims(h):
+    out = np.zeros(15, dtype=np.int32)
+    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 15), "qg_problem_dims")
+    keys = ("N", "L", "G", "T", "M", "K", "Lp", "Kp", "Np", "N4", "Tp", "nLb", "nKb",
+            "ctg_bl", "ctg_wl")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def qg_set_ctg_tile(h, bl, wl):
+    _check(lib.qg_set_ctg_tile(h, bl, wl), "qg_set_ctg_tile")
+
+
+def qg_eval_grad(h, d_x, d_grad, d_terms, hom, d_ws, stream):
+    _check(lib.qg_eval_grad(h, d_x, d_grad, d_terms, C.byref(hom), d_ws, stream),
+           "qg_eval_grad")
+
+
+def qg_adam_step(h, d_x, d_m, d_v, d_g, it, lr, cfg, stream):
+    arr = (C.c_double * QG_NCLASS)(*[float(a) for a in lr])
+    _check(lib.qg_adam_step(h, d_x, d_m, d_v, d_g, int(it), arr, C.byref(cfg), stream),
+           "qg_adam_step")
+
+
+def qg_solve(h, d_x, d_m, d_v, opts, cfg, d_ws, stream):
+    rep = qg_solve_report()
+    _check(lib.qg_solve(h, d_x, d_m, d_v, C.byref(opts), C.byref(cfg), C.byref(rep), d_ws,
+                        stream), "qg_solve")
+    return rep
+
+
+def qg_debug_fetch(h, d_ws, name, host_array, stream):
+    _check(lib.qg_debug_fetch(h, d_ws, name.encode(), host_array.ctypes.data_as(_vp),
+                              host_array.nbytes, stream), "qg_debug_fetch")
+    return host_array
+
+
+def qg_destroy_problem(h):
+    lib.qg_destroy_problem(h)
+
+
+# ---------------------------------------------------------------- owner class
+
+def solve_opts(n_steps, alpha0, alphaf=None, iter0=0, n_total=0, check_every=0, eps0=1e-2,
+               epsf=1e-2, beta0=1.0, betaf=1.0, rho0=1.0, rhof=1.0, z_ed=0.0,
+               stop_ratio=0.99, use_graph=1, profile=0):
+    alpha0 = list(alpha0) if np.ndim(alpha0) else [float(alpha0)] * QG_NCLASS
+    alphaf = alpha0 if alphaf is None else (
+        list(alphaf) if np.ndim(alphaf) else [float(alphaf)] * QG_NCLASS)
+    return qg_solve_opts(
+        n_steps=n_steps, iter0=iter0, n_total=n_total, check_every=check_every,
+        alpha0=(C.c_double * QG_NCLASS)(*alpha0), alphaf=(C.c_double * QG_NCLASS)(*alphaf),
+        eps0=eps0, epsf=epsf, beta0=beta0, betaf=betaf, rho0=rho0, rhof=rhof, z_ed=z_ed,
+        stop_ratio=stop_ratio, use_graph=use_graph, profile=profile)
+
+
+def adam_cfg(beta1=0.9, beta2=0.999, eps=1e-8, eps_in_numerator=False):
+    return qg_adam_cfg(beta1=beta1, beta2=beta2, eps=eps,
+                       eps_in_numerator=1 if eps_in_numerator else 0)
+
+
+class Problem:
+    """Device buffers and handle of one built problem (torch tensors on a GPU)."""
+
+    def __init__(self, case, device="cuda", ctg_mode=QG_CTG_LIST, ctg_list=None, flags=0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.case = case
+        desc, keep1 = grid_desc(case)
+        opts, keep2 = build_opts(case, ctg_mode=ctg_mode, ctg_list=ctg_list, flags=flags)
+        self.sizes = qg_problem_sizes(desc, opts)
+        self.arena = torch.empty(max(self.sizes.const_bytes, 256), dtype=torch.uint8,
+                                 device=self.device)
+        self.workspace = torch.empty(max(self.sizes.workspace_bytes, 256), dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream
+        self.handle = qg_build_problem(desc, opts, self.arena.data_ptr(),
+                                       self.sizes.const_bytes, self._stream())
+        del keep1, keep2
+        self.n_x = int(self.sizes.n_x)
+        self.dims = qg_problem_dims(self.handle)
+        self.K = self.dims["K"]
+
+    def _stream(self):
+        s = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        return s.cuda_stream
+
+    def layout(self):
+        lay = qg_layout_of(self.handle)
+        return list(lay.off), list(lay.len)
+
+    def ctg_list(self):
+        return qg_ctg_list(self.handle, self.K)
+
+    def set_ctg_tile(self, bl, wl):
+        qg_set_ctg_tile(self.handle, bl, wl)
+        self.dims = qg_problem_dims(self.handle)
+
+    def new_vector(self, host=None):
+        t = self.torch.zeros(self.n_x, dtype=self.torch.float64, device=self.device)
+        if host is not None:
+            t.copy_(self.torch.as_tensor(np.asarray(host, dtype=np.float64)))
+        return t
+
+    def eval_grad(self, x, eps, beta=1.0, rho_scale=1.0, grad=True):
+        torch = self.torch
+        g = torch.empty(self.n_x, dtype=torch.float64, device=self.device) if grad else None
+        terms = torch.empty(32, dtype=torch.float64, device=self.device)  # 256 B aligned
+        qg_eval_grad(self.handle, x.data_ptr(), g.data_ptr() if g is not None else None,
+                     terms.data_ptr(), qg_homotopy(eps, beta, rho_scale),
+                     self.workspace.data_ptr(), self._stream())
+        return terms[:QG_NTERMS], g
+
+    def adam_step(self, x, m, v, g, it, lr, cfg=None):
+        cfg = cfg or adam_cfg()
+        lr = list(lr) if np.ndim(lr) else [float(lr)] * QG_NCLASS
+        qg_adam_step(self.handle, x.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr(), it,
+                     lr, cfg, self._stream())
+
+    def solve(self, x, m, v, opts, cfg=None):
+        cfg = cfg or adam_cfg()
+        return qg_solve(self.handle, x.data_ptr(), m.data_ptr(), v.data_ptr(), opts, cfg,
+                        self.workspace.data_ptr(), self._stream())
+
+    def fetch(self, name, shape):
+        out = np.empty(shape, dtype=np.float64)
+        return qg_debug_fetch(self.handle, self.workspace.data_ptr(), name, out, self._stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            qg_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def report_dict(rep):
+    return dict(steps_done=rep.steps_done, steps_to_gap=rep.steps_to_gap, wall_s=rep.wall_s,
+                time_to_gap_s=rep.time_to_gap_s, final_loss=rep.final_loss,
+                final_score=rep.final_score,
+                terms=dict(zip(TERM_NAMES, list(rep.terms))),
+                kernel_ms=dict(zip(KERNEL_NAMES, list(rep.kernel_ms)[:6])),
+                kernel_calls=dict(zip(KERNEL_NAMES, list(rep.kernel_calls)[:6])))

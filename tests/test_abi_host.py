@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every symbol qg.h declares, and its
+host-only entry point (qg_problem_sizes) validates inputs.  No GPU needed."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import network
+from paper_2310_06650_amd import synth
+from tests._cases import tiny_case
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+qg = pytest.importorskip("paper_2310_06650_amd.qg",
+                         reason="libqg.so not built (run __graft_entry__.build())")
+
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "qg.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qg_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(qg.lib, n), n
+        assert n in qg.EXPORTED, n
+
+
+def test_status_strings():
+    assert qg.lib.qg_status_string(0) == b"ok"
+    assert b"topology" in qg.lib.qg_status_string(qg.QG_ERR_TOPOLOGY)
+
+
+def _sizes(case, mode=None, ctg=None, **kw):
+    desc, k1 = qg.grid_desc(case)
+    if mode is None:
+        mode = qg.QG_CTG_LIST
+    opts, k2 = qg.build_opts(case, ctg_mode=mode, ctg_list=ctg, **kw)
+    return qg.qg_problem_sizes(desc, opts)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_sizes_and_contingency_count(name):
+    c = synth.config_case(name)
+    s = _sizes(c)
+    assert s.n_x == c.n_x and s.n_ctg == c.n_ctg
+    assert s.const_bytes > 0 and s.workspace_bytes > 0
+    s_all = _sizes(c, mode=qg.QG_CTG_ALL_NONBRIDGE)
+    br = network.bridges_bruteforce(c.n_bus, c.br_from, c.br_to) if name == "c1" else None
+    if br is not None:
+        assert s_all.n_ctg == int((~br).sum())
+
+
+def test_tree_grid_has_no_contingencies():
+    c = tiny_case(4, [0, 1, 2], [1, 2, 3], [0.1, 0.1, 0.1], [0])
+    s = _sizes(c, mode=qg.QG_CTG_ALL_NONBRIDGE)
+    assert s.n_ctg == 0
+
+
+def _expect(status, fn):
+    with pytest.raises(qg.QgError) as e:
+        fn()
+    assert e.value.status == status, str(e.value)
+
+
+def test_disconnected_grid_is_topology_error():
+    c = tiny_case(4, [0, 2], [1, 3], [0.1, 0.1], [0])
+    _expect(qg.QG_ERR_TOPOLOGY, lambda: _sizes(c, mode=qg.QG_CTG_ALL_NONBRIDGE))
+
+
+def test_listed_bridge_is_topology_error():
+    c = tiny_case(4, [0, 1, 2, 0], [1, 2, 3, 2], [0.1] * 4, [0])
+    # branch 2 (2-3) is a bridge
+    _expect(qg.QG_ERR_TOPOLOGY, lambda: _sizes(c, ctg=[0, 2]))
+    assert _sizes(c, ctg=[0, 1, 3]).n_ctg == 3
+
+
+def test_bad_values_are_arg_errors():
+    c = tiny_case(3, [0, 1, 0], [1, 2, 2], [0.1, 0.1, 0.1], [0])
+    bad = tiny_case(3, [0, 1, 0], [1, 2, 2], [0.1, -0.1, 0.1], [0])
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(bad, ctg=[]))
+    oob = tiny_case(3, [0, 1, 0], [1, 5, 2], [0.1, 0.1, 0.1], [0])
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(oob, ctg=[]))
+    loop = tiny_case(3, [0, 1, 0], [1, 1, 2], [0.1, 0.1, 0.1], [0])
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(loop, ctg=[]))
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(c, ctg=[0, 0]))
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(c, ctg=[7]))
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(c, ctg=[], ref_bus=9))
+    c.gen_pmin = c.gen_pmax * 2
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(c, ctg=[]))
+    long_t = tiny_case(3, [0, 1, 0], [1, 2, 2], [0.1, 0.1, 0.1], [0], T=65)
+    _expect(qg.QG_ERR_ARG, lambda: _sizes(long_t, ctg=[]))
+
+
+def test_parallel_branches_are_not_bridges():
+    c = tiny_case(3, [0, 0, 1], [1, 1, 2], [0.1, 0.2, 0.1], [0])
+    s = _sizes(c, mode=qg.QG_CTG_ALL_NONBRIDGE)
+    assert s.n_ctg == 2   # the two parallel 0-1 branches; 1-2 is a bridge
+
+
+def test_null_arguments():
+    _expect(qg.QG_ERR_ARG, lambda: qg.qg_problem_sizes(qg.qg_grid_desc(), qg.qg_build_opts()))

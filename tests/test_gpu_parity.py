@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerance: the objective terms and every variable class of the gradient agree
+to 1e-9 relative (normwise per class: max|g - g_ref| / max|g_ref|).  Test points
+are seeded interior points of the box, away from the measure-zero kinks.
+"""
+import numpy as np
+import pytest
+
+from oracle import adam as oadam
+from oracle import objective as ob
+from oracle import solve as osolve
+from paper_2310_06650_amd import synth
+from tests._cases import tiny_case
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def qg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_06650_amd import qg as _qg
+    return _qg
+
+
+_models = {}
+
+
+def oracle_model(case):
+    key = id(case)
+    if key not in _models:
+        _models[key] = ob.make_model(case)
+    return _models[key]
+
+
+def assert_terms_close(qg, got, ref, tol=TOL):
+    got = dict(zip(qg.TERM_NAMES, got))
+    scale = sum(abs(ref[k]) for k in ob.TERMS)
+    for k in ob.TERMS + ("total",):
+        err = abs(got[k] - ref[k])
+        assert err <= tol * max(abs(ref[k]), 1e-12 * scale), (k, got[k], ref[k], err)
+
+
+def assert_grad_close(case, g, g_ref, tol=TOL):
+    names = ("v", "theta", "p", "q", "r", "u")
+    for name, s in zip(names, case.block_slices()):
+        den = np.abs(g_ref[s]).max()
+        err = np.abs(g[s] - g_ref[s]).max() / max(den, 1e-300)
+        assert err <= tol, (name, err, den)
+
+
+def gpu_eval(qg, prob, x, eps, beta, rho):
+    import torch
+    xd = prob.new_vector(x)
+    terms, g = prob.eval_grad(xd, eps, beta, rho)
+    torch.cuda.synchronize()
+    return terms.cpu().numpy(), g.cpu().numpy()
+
+
+CASES = {}
+
+
+def case(name):
+    if name not in CASES:
+        CASES[name] = synth.config_case(name)
+    return CASES[name]
+
+
+@pytest.mark.parametrize("seed,eps,beta,rho", [(1, 1e-2, 1.0, 1.0), (2, 0.3, 0.4, 0.7),
+                                               (3, 0.0, 1.0, 1.0)])
+def test_terms_and_gradient_c1(qg, seed, eps, beta, rho):
+    c = case("c1")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, seed)
+    t, g = gpu_eval(qg, prob, x, eps, beta, rho)
+    tr, gr = ob.evaluate(oracle_model(c), x, eps, beta, rho)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+
+
+@pytest.mark.parametrize("which", ["random", "flat"])
+def test_terms_and_gradient_c2(qg, which):
+    c = case("c2")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, 5, spread=0.3) if which == "random" else synth.flat_start(c)
+    t, g = gpu_eval(qg, prob, x, 1e-2, 0.8, 1.0)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 0.8, 1.0)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+
+
+def test_intermediates_c2(qg):
+    """Base-case DC flows, reactive maxima, balance multipliers and the
+    per-contingency penalties z_tk against the oracle's own algebra."""
+    c = case("c2")
+    m = oracle_model(c)
+    prob = qg.Problem(c)
+    d = prob.dims
+    x = synth.random_point(c, 8, spread=0.3)
+    eps, beta = 2e-2, 0.9
+    gpu_eval(qg, prob, x, eps, beta, 1.0)
+    T, L, K, N = c.n_period, c.n_branch, c.n_ctg, c.n_bus
+    F = prob.fetch("F", (T, d["Lp"]))[:, :L]
+    V, TH, P, Q, R, U = ob.unpack(c, x)
+    Fr = ob.balanced_injection(c, P) @ m.isf.T
+    np.testing.assert_allclose(F, Fr, rtol=0, atol=1e-12 * np.abs(Fr).max())
+    fl = ob.branch_flows(m, V, TH)
+    q2r, _ = ob.qmax2(fl)
+    q2 = prob.fetch("q2", (T, d["Lp"]))[:, :L]
+    np.testing.assert_allclose(q2, q2r, rtol=1e-12, atol=1e-15)
+    _, _, zr = _oracle_z(m, x, eps, beta)
+    z = prob.fetch("zval", (T, d["Kp"]))[:, :K]
+    np.testing.assert_allclose(z, zr, rtol=1e-10)
+
+
+def _oracle_z(m, x, eps, beta):
+    c = m.case
+    V, TH, P, Q, R, U = ob.unpack(c, x)
+    fl = ob.branch_flows(m, V, TH)
+    q2, _ = ob.qmax2(fl)
+    F = ob.balanced_injection(c, P) @ m.isf.T
+    z = np.zeros((c.n_period, len(m.ctg)))
+    for t in range(c.n_period):
+        Pk = F[t][:, None] + m.lodf * F[t, m.ctg][None, :]
+        s = np.sqrt(Pk * Pk + q2[t][:, None])
+        sig = ob.soft_relu(s - c.br_smax_ctg[:, None], eps)
+        sig[m.ctg, np.arange(len(m.ctg))] = 0.0
+        z[t] = c.dt[t] * c.c_s * beta * sig.sum(axis=0)
+    return F, q2, z
+
+
+def test_bitwise_deterministic(qg):
+    c = case("c2")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, 9, spread=0.3)
+    t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    t2, g2 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    assert np.array_equal(t1, t2) and np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("bl,wl", [(8, 2), (8, 4), (16, 1), (16, 4), (32, 2), (32, 8)])
+def test_ctg_tile_invariance(qg, bl, wl):
+    c = case("c2")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, 10, spread=0.3)
+    t0, g0 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    prob.set_ctg_tile(bl, wl)
+    t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    np.testing.assert_allclose(t1, t0, rtol=1e-12)
+    assert_grad_close(c, g1, g0, tol=1e-12)
+
+
+def test_adam_step_matches_oracle(qg):
+    """Alg. 3 elementwise; the tolerance scales with the magnitude of the
+    summands, since b1 m and (1 - b1) g may cancel (the kernel fuses
+    multiply-adds, NumPy rounds each product)."""
+    import torch
+    c = case("c2")
+    prob = qg.Problem(c)
+    rng = np.random.default_rng(4)
+    x = synth.random_point(c, 11)
+    g = rng.normal(size=c.n_x) * 10.0 ** rng.integers(-4, 5, size=c.n_x)
+    m0 = rng.normal(size=c.n_x) * 0.1
+    v0 = np.abs(rng.normal(size=c.n_x))
+    lr = [1e-3, 2e-3, 3e-3, 4e-3, 5e-3, 6e-3]
+    lo, hi = oadam.box_bounds(c)
+    for eps_num in (False, True):
+        xd, md, vd, gd = (prob.new_vector(a) for a in (x, m0, v0, g))
+        prob.adam_step(xd, md, vd, gd, 7, lr, qg.adam_cfg(eps_in_numerator=eps_num))
+        torch.cuda.synchronize()
+        xr, mr, vr = oadam.adam_update(x, m0, v0, g, 7, osolve.class_vector(c, lr), lo, hi,
+                                       eps_in_numerator=eps_num)
+        mscale = 0.9 * np.abs(m0) + 0.1 * np.abs(g)
+        vscale = 0.999 * v0 + 0.001 * g * g
+        assert (np.abs(md.cpu().numpy() - mr) <= 4e-16 * mscale).all()
+        assert (np.abs(vd.cpu().numpy() - vr) <= 4e-16 * vscale).all()
+        lrv = osolve.class_vector(c, lr)
+        assert (np.abs(xd.cpu().numpy() - xr) <= 1e-12 * lrv + 4e-16 * np.abs(xr)).all()
+
+
+def _sched_opts(n, alpha0, alphaf, eps0=1e-2, epsf=1e-3):
+    return dict(eps0=eps0, epsf=epsf, beta0=0.5, betaf=1.0, rho0=0.5, rhof=1.0,
+                alpha0=alpha0, alphaf=alphaf, n_total=n)
+
+
+def test_solve_trajectory_c1(qg):
+    """200 Adam steps (lr 1e-3) of the solve loop, one call per step (resume
+    through iter0).
+
+    The loop is chaotic: relative gradient noise of 1e-13 in the oracle's own
+    loop grows to ~1e-2 in x by step 200 (Adam's normalised steps flip sign
+    where a gradient oscillates around zero).  So (a) the free-running
+    trajectories agree to 1e-9 over the first 50 steps, where that noise is
+    still below 1e-13, and (b) every one of the 200 steps is checked by
+    shadowing: the oracle's step taken from the GPU's own state (x, m, v)
+    must match the GPU's next state to 1e-9.
+    """
+    import torch
+    c = case("c1")
+    m = oracle_model(c)
+    prob = qg.Problem(c)
+    n = 200
+    sopt = _sched_opts(n, [1e-3] * 6, [1e-3] * 6)
+    x0 = synth.flat_start(c)
+    rec = []
+    osolve.run(m, x0, 50, sopt, record=rec)
+    xd = prob.new_vector(x0)
+    md = prob.new_vector()
+    vd = prob.new_vector()
+    common = dict(n_total=n, eps0=sopt["eps0"], epsf=sopt["epsf"], beta0=0.5, betaf=1.0,
+                  rho0=0.5, rhof=1.0, use_graph=0)
+    lo, hi = oadam.box_bounds(c)
+    x_prev = x0.copy()
+    m_prev = np.zeros_like(x0)
+    v_prev = np.zeros_like(x0)
+    for i in range(n):
+        prob.solve(xd, md, vd, qg.solve_opts(1, [1e-3] * 6, iter0=i, **common))
+        torch.cuda.synchronize()
+        xi, mi, vi = (t.cpu().numpy() for t in (xd, md, vd))
+        if i < 50:
+            assert np.abs(xi - rec[i]).max() <= 1e-9 * np.abs(rec[i]).max(), ("free", i)
+        eps, beta, rho, alpha = osolve.schedule(i + 1, n, sopt)
+        _, g = ob.evaluate(m, x_prev, eps, beta, rho)
+        xs, ms, vs = oadam.adam_update(x_prev, m_prev, v_prev, g, i + 1,
+                                       osolve.class_vector(c, alpha), lo, hi)
+        assert np.abs(xi - xs).max() <= 1e-9 * np.abs(xs).max(), ("shadow x", i)
+        assert np.abs(mi - ms).max() <= 1e-9 * np.abs(ms).max(), ("shadow m", i)
+        x_prev, m_prev, v_prev = xi, mi, vi
+
+
+def test_graph_replay_equals_eager(qg):
+    import torch
+    c = case("c2")
+    prob = qg.Problem(c)
+    x0 = synth.flat_start(c)
+    outs = []
+    for use_graph in (0, 1):
+        xd = prob.new_vector(x0)
+        md = prob.new_vector()
+        vd = prob.new_vector()
+        rep = prob.solve(xd, md, vd, qg.solve_opts(40, [1e-3] * 6, alphaf=[1e-4] * 6,
+                                                   eps0=1e-1, epsf=1e-3, use_graph=use_graph))
+        torch.cuda.synchronize()
+        outs.append((xd.cpu().numpy(), md.cpu().numpy(), vd.cpu().numpy(), rep.final_loss))
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(a, b)
+    assert outs[0][3] == outs[1][3]
+
+
+def test_no_contingency_grid(qg):
+    """A radial grid has no non-islanding outage: K = 0, C_ctg = 0."""
+    c = tiny_case(5, [0, 1, 2, 1], [1, 2, 3, 4], [0.1, 0.2, 0.1, 0.15], [0, 3], T=3,
+                  br_r=[0.01] * 4)
+    prob = qg.Problem(c, ctg_mode=qg.QG_CTG_ALL_NONBRIDGE)
+    assert prob.K == 0
+    x = synth.random_point(c, 2)
+    t, g = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+
+
+@pytest.mark.parametrize("T", [1, 17, 33, 48])
+def test_ragged_sizes(qg, T):
+    """Sizes that are not multiples of any tile: N=37, L=71, K ragged, T odd."""
+    c = synth.make_case(seed=40 + T, n_bus=37, n_branch=71, n_gen=9, n_period=T, n_ctg=None)
+    prob = qg.Problem(c)
+    x = synth.random_point(c, T)
+    t, g = gpu_eval(qg, prob, x, 5e-2, 0.9, 0.8)
+    tr, gr = ob.evaluate(oracle_model(c), x, 5e-2, 0.9, 0.8)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+
+
+def test_misaligned_buffer_rejected(qg):
+    import torch
+    c = case("c1")
+    prob = qg.Problem(c)
+    buf = torch.zeros(c.n_x + 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(qg.QgError) as e:
+        qg.qg_eval_grad(prob.handle, buf.data_ptr() + 8, None, None, qg.qg_homotopy(1e-2, 1, 1),
+                        prob.workspace.data_ptr(), prob._stream())
+    assert e.value.status == qg.QG_ERR_ARG
