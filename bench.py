@@ -55,9 +55,9 @@ def kernel_work(case, dims):
         # ISF product: 2 T N L flop
         "k_balance_flow": ("mfma", 2.0 * T * (N - 1) * L, "flop"),
         "k_adjoint": ("mfma", 2.0 * T * (N - 1) * L, "flop"),
-        # per-period partials over K contingencies and L branches
-        "k_ctg_finalize": ("hbm", D * T * (K * dims["nLb"] * 2 + L * dims["nKb"] * 2
-                                           + 3 * L), "byte"),
+        # partial sums over l-blocks for every (t, k), over k-blocks for every (t, l)
+        "k_ctg_zred": ("hbm", D * T * K * (dims["nLb"] * 2 + 2), "byte"),
+        "k_ctg_asm": ("hbm", D * T * L * (dims["nKb"] * 2 + 6), "byte"),
         "k_forward": ("hbm", D * (2 * T * N + 4 * T * G + T * L * 15), "byte"),
         "k_final": ("hbm", D * (T * 2 * L * 2 + 3 * (2 * T * N + 4 * T * G)), "byte"),
     }
@@ -107,8 +107,8 @@ def main():
     case = synth.config_case(args.config)
     prob = qg.Problem(case, device="cuda:0")
     if args.ctg_tile:
-        bl, wl = (int(v) for v in args.ctg_tile.split("x"))
-        prob.set_ctg_tile(bl, wl)
+        parts = [int(v) for v in args.ctg_tile.split("x")]
+        prob.set_ctg_tile(*parts)
     stream = torch.cuda.Stream()
     prob.stream = stream
     x0 = synth.flat_start(case)
@@ -138,7 +138,7 @@ def main():
     prof = prob.solve(xp, mp, vp, qg.solve_opts(args.profile_steps, alpha0, alphaf,
                                                 iter0=args.warmup, profile=1, **common))
     torch.cuda.synchronize()
-    kms = dict(zip(qg.KERNEL_NAMES, list(prof.kernel_ms)[:6]))
+    kms = dict(zip(qg.KERNEL_NAMES, list(prof.kernel_ms)[:len(qg.KERNEL_NAMES)]))
     work = kernel_work(case, prob.dims)
     dom = max(kms, key=lambda k: kms[k])
     bound, amount, unit = work[dom]
@@ -162,7 +162,7 @@ def main():
                                     f"{case.n_ctg}-contingency synthetic grid ({args.config})",
                            n_bus=case.n_bus, n_branch=case.n_branch, n_gen=case.n_gen,
                            n_period=case.n_period, n_ctg=case.n_ctg,
-                           ctg_tile=f"{prob.dims['ctg_bl']}x{prob.dims['ctg_wl']}",
+                           ctg_tile=f"{prob.dims['ctg_bl']}x{prob.dims['ctg_wl']}x{prob.dims['ctg_tc']}",
                            parallelism="single GPU"),
                kernel_us={k: round(v * 1e3, 3) for k, v in kms.items()},
                final_score=rep.final_score, roofline=roof)

@@ -238,32 +238,34 @@ qg_status qg_solve(qg_problem* prob, double* d_x, double* d_m, double* d_v,
                    qg_solve_report* report, void* d_workspace, void* stream);
 
 /*
- * Padded sizes and launch geometry, for tests and tools: dims[0..14] =
- * N, L, G, T, M, K, Lp, Kp, Np, N4, Tp, nLb, nKb, ctg_bl, ctg_wl
- * (Lp = L rounded up to 64, Kp = K up to 64, Np = N up to 16, N4 = N up to 4,
+ * Padded sizes and launch geometry, for tests and tools: dims[0..15] =
+ * N, L, G, T, M, K, Lp, Kp, G16, G4, Tp, nLb, nKb, ctg_bl, ctg_wl, ctg_tc
+ * (Lp = L rounded up to 64, Kp = K up to 64, G16 = G up to 16, G4 = G up to 4,
  * Tp = T up to 16; nLb, nKb = partial-sum counts of the contingency
- * map-reduce; ctg_bl, ctg_wl = its tile).  capacity must be >= 15.
+ * map-reduce; ctg_bl, ctg_wl, ctg_tc = its tile).  capacity must be >= 16.
  */
 qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacity);
 
 /*
- * Tile of the contingency map-reduce: bl branches per wavefront (8, 16 or 32)
- * and wl wavefronts per block (1, 2, 4 or 8), with bl*wl >= 16.  The results
- * do not depend on the tile except through the order of floating-point sums.
- * Used by the autotuner.  Errors: ARG.
+ * Tile of the contingency map-reduce: bl branches per wavefront (8, 16 or 32),
+ * wl wavefronts per block (1, 2, 4 or 8) with bl*wl >= 16, and tc periods per
+ * block (0: a default from the problem size; at most 8 and at most what the
+ * LDS staging budget allows).  The results do not depend on the tile except through the order
+ * of floating-point sums.  Used by the autotuner.  Errors: ARG.
  */
-qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl);
+qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
 
 /*
  * Test support: copy an intermediate array of the last evaluation from the
  * workspace into host memory (synchronises the stream).  Names and shapes
  * (row-major, padded sizes from qg_problem_dims):
  *   "F" [T][Lp] base-case DC flows      "Fk" [T][Kp] flows of outaged branches
- *   "q2" [T][Lp] max(q_fr^2, q_to^2)    "pbarT" [N4][Tp] balanced injections
+ *   "q2" [T][Lp] max(q_fr^2, q_to^2)    "psum" [T] total generator output
  *   "lamp", "lamq" [T][N] balance multipliers
  *   "zval" [T][Kp] contingency penalties z_tk
- *   "gfT" [Lp][Tp] dL/dF                "gpb" [T][Np] dL/dp_bar before the
- *   "qtot" [T][Lp] dL/d max(q^2)                       uniform-slack correction
+ *   "gfT" [Lp][Tp] dL/dF                "qtot" [T][Lp] dL/d max(q^2)
+ *   "gpdc" [nsplit][T][G16] partial sums of the DC part of dL/dp (without
+ *          the worst contingency's own outage term)
  *   "params" [16] step parameter block  "terms" [QG_NTERMS]
  * bytes must not exceed the array's size.  Errors: ARG, DEVICE.
  */

@@ -122,23 +122,28 @@ qg_status qg_ctg_list(const qg_problem* pr, int32_t* out, int32_t capacity) {
 qg_status qg_problem_dims(const qg_problem* pr, int32_t* d, int32_t capacity) {
   qg_status s = check_problem(pr);
   if (s != QG_OK) return s;
-  if (!d || capacity < 15) return fail(QG_ERR_ARG, "dims needs 15 entries");
+  if (!d || capacity < 16) return fail(QG_ERR_ARG, "dims needs 16 entries");
   const qg::Problem& p = pr->p;
-  const int32_t v[15] = {p.N, p.L, p.G, p.T, p.M, p.K, p.Lp, p.Kp, p.Np, p.N4, p.Tp,
-                         p.nLb, p.nKb, p.tile.bl, p.tile.wl};
+  const int32_t v[16] = {p.N, p.L, p.G, p.T, p.M, p.K, p.Lp, p.Kp, p.G16, p.G4, p.Tp,
+                         p.nLb, p.nKb, p.tile.bl, p.tile.wl, p.tile.tc};
   std::memcpy(d, v, sizeof(v));
   return QG_OK;
 }
 
-qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl) {
+qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl, int32_t tc) {
   qg_status s = check_problem(pr);
   if (s != QG_OK) return s;
   if (!(bl == 8 || bl == 16 || bl == 32) || !(wl == 1 || wl == 2 || wl == 4 || wl == 8) ||
       bl * wl < 16)
     return fail(QG_ERR_ARG, "tile must have bl in {8,16,32}, wl in {1,2,4,8}, bl*wl >= 16");
   qg::Problem& p = pr->p;
-  p.tile = qg::CtgTile{bl, wl};
   const int span = bl * wl;
+  if (tc <= 0) tc = qg::default_ctg_tc(p.T, span);
+  if (tc > p.T) tc = p.T;
+  if (tc > qg::kCtgMaxTc) return fail(QG_ERR_ARG, "at most 8 periods per block");
+  if (tc * (2 * span + qg::kCtgLanes) > qg::kCtgStageDoubles)
+    return fail(QG_ERR_ARG, "period chunk too large for the LDS staging budget");
+  p.tile = qg::CtgTile{bl, wl, tc};
   p.nLb = (p.Lp + span - 1) / span;
   return QG_OK;
 }
@@ -233,16 +238,40 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     (void)hipEventDestroy(ev);
   }
 
+  // the kernels read each step's homotopy and step sizes from the schedule
+  // table; the captured graphs depend only on the Adam constants
   qg::EvalMode sm;
   std::memset(&sm, 0, sizeof(sm));  // memcmp below compares padding too
   sm.schedule = 1;
-  sm.n_total = n_total;
-  for (int c = 0; c < QG_NCLASS; ++c) { sm.alpha0[c] = o->alpha0[c]; sm.alphaf[c] = o->alphaf[c]; }
-  sm.eps0 = o->eps0; sm.epsf = o->epsf;
-  sm.beta0 = o->beta0; sm.betaf = o->betaf;
-  sm.rho0 = o->rho0; sm.rhof = o->rhof;
   sm.adam_b1 = cfg->beta1; sm.adam_b2 = cfg->beta2; sm.adam_eps = cfg->eps;
   sm.eps_in_num = cfg->eps_in_numerator;
+
+  // eqs. (norm_t)-(step_size) indexed by the iteration i (t0 = 0, tf = n_total)
+  std::vector<double> table((size_t)qg::kSchedCap * qg::kSchedStride, 0.0);
+  auto fill = [&](int64_t first, int count) {
+    const double n = (double)n_total;
+    for (int q = 0; q < count; ++q) {
+      const double i = (double)(first + q);
+      const double th = 2.0 * i / n - 1.0;
+      const double e = std::exp(4.0 * th);
+      const double sc = e / (0.6 + e);
+      double* row = &table[(size_t)q * qg::kSchedStride];
+      row[0] = o->eps0 * std::pow(10.0, sc * std::log10(o->epsf / o->eps0));
+      row[1] = o->beta0 + (o->betaf - o->beta0) * (i / n);
+      row[2] = o->rho0 + (o->rhof - o->rho0) * (i / n);
+      for (int c = 0; c < QG_NCLASS; ++c)
+        row[3 + c] = o->alpha0[c] * std::pow(10.0, sc * std::log10(o->alphaf[c] / o->alpha0[c]));
+      row[9] = 1.0 - std::pow(cfg->beta1, i);
+      row[10] = 1.0 - std::pow(cfg->beta2, i);
+    }
+  };
+  auto upload = [&](int64_t first, int count) -> qg_status {
+    fill(first, count);
+    HIP_TRY(hipMemcpyAsync(w.sched, table.data(), (size_t)count * qg::kSchedStride * sizeof(double),
+                           hipMemcpyHostToDevice, ex), "schedule upload");
+    if (qg::launch_set_step(&p, w, 0, ex) != 0) return hip_fail(hipGetLastError(), "launch");
+    return QG_OK;
+  };
 
   qg::EvalMode score{};
   score.schedule = 0;
@@ -254,18 +283,19 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   rep->steps_to_gap = -1;
   rep->time_to_gap_s = -1.0;
 
-  if (qg::launch_set_step(&p, w, o->iter0, ex) != 0) return hip_fail(hipGetLastError(), "launch");
-
   const bool profile = o->profile != 0;
   const bool graph = o->use_graph != 0 && !profile;
   hipEvent_t evs[QG_NKERNELS];
+  constexpr int kKernels = 7;
   if (profile)
-    for (int i = 0; i < 7; ++i) HIP_TRY(hipEventCreate(&evs[i]), "event");
+    for (int i = 0; i <= kKernels; ++i) HIP_TRY(hipEventCreate(&evs[i]), "event");
 
-  // graph of gsteps consecutive steps (the step counter lives on the device)
-  const int gsteps = 8;
+  // graph of gsteps consecutive steps (the step counter lives on the device);
+  // one graph launch costs about as much as several kernels, so it covers
+  // up to 32 steps
+  const int gsteps = (int)std::min<int64_t>(32, o->n_steps);
   hipGraphExec_t gexec = static_cast<hipGraphExec_t>(pr->p.graph_exec);
-  if (graph && o->n_steps >= gsteps) {
+  if (graph && gsteps >= 4) {
     const void* key[5] = {d_x, d_m, d_v, d_workspace, nullptr};
     bool hit = gexec && std::memcmp(key, pr->p.graph_key, sizeof(key)) == 0 &&
                pr->p.graph_steps == gsteps;
@@ -302,8 +332,8 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
                               profile ? reinterpret_cast<void**>(evs) : nullptr);
       if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
       if (profile) {
-        HIP_TRY(hipEventSynchronize(evs[6]), "event sync");
-        for (int q = 0; q < 6; ++q) {
+        HIP_TRY(hipEventSynchronize(evs[kKernels]), "event sync");
+        for (int q = 0; q < kKernels; ++q) {
           float ms = 0.f;
           HIP_TRY(hipEventElapsedTime(&ms, evs[q], evs[q + 1]), "elapsed");
           rep->kernel_ms[q] += ms;
@@ -328,6 +358,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   while (done < o->n_steps) {
     int64_t n = o->n_steps - done;
     if (o->check_every > 0) n = std::min(n, o->check_every - (done % o->check_every));
+    n = std::min<int64_t>(n, qg::kSchedCap);
+    s = upload(o->iter0 + done + 1, (int)n);
+    if (s != QG_OK) return s;
     s = run_steps(n);
     if (s != QG_OK) return s;
     done += n;
@@ -355,9 +388,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   if (s != QG_OK) return s;
   rep->final_score = -tot;
   if (profile) {
-    for (int q = 0; q < 6; ++q)
+    for (int q = 0; q < kKernels; ++q)
       if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
-    for (int i = 0; i < 7; ++i) (void)hipEventDestroy(evs[i]);
+    for (int i = 0; i <= kKernels; ++i) (void)hipEventDestroy(evs[i]);
   }
   return QG_OK;
 }
@@ -373,10 +406,11 @@ qg_status qg_debug_fetch(const qg_problem* pr, const void* d_workspace, const ch
   struct Item { const char* n; const void* ptr; size_t bytes; };
   const Item items[] = {
       {"F", w.F, (size_t)p.T * p.Lp * D},       {"Fk", w.Fk, (size_t)p.T * p.Kp * D},
-      {"q2", w.q2, (size_t)p.T * p.Lp * D},     {"pbarT", w.pbarT, (size_t)p.N4 * p.Tp * D},
+      {"q2", w.q2, (size_t)p.T * p.Lp * D},     {"psum", w.psum, (size_t)p.T * D},
       {"lamp", w.lamp, (size_t)p.T * p.N * D},  {"lamq", w.lamq, (size_t)p.T * p.N * D},
       {"zval", w.zval, (size_t)p.T * p.Kp * D}, {"gfT", w.gfT, (size_t)p.Lp * p.Tp * D},
-      {"gpb", w.gpb, (size_t)p.T * p.Np * D},   {"qtot", w.qtot, (size_t)p.T * p.Lp * D},
+      {"gpdc", w.gpdc, (size_t)p.nsplit * p.T * p.G16 * D},
+      {"qtot", w.qtot, (size_t)p.T * p.Lp * D},
       {"params", w.params, (size_t)qg::kParams * D}, {"terms", w.terms, (size_t)QG_NTERMS * D}};
   for (const Item& it : items) {
     if (std::strcmp(it.n, name) != 0) continue;

@@ -91,15 +91,17 @@ bool find_bridges(int N, int L, const int32_t* fr, const int32_t* to,
 
 // Byte layout of the constant arena.  The same walk gives the size (for
 // qg_problem_sizes) and the offsets (for the image).
+constexpr int kNConst = 46;
+
 struct ConstLayout {
-  size_t off[44];
+  size_t off[kNConst];
   size_t total;
 };
 
 ConstLayout const_layout(const Problem& p) {
   const size_t I = sizeof(int32_t), D = sizeof(double);
   const size_t N = p.N, L = p.L, G = p.G, T = p.T, M = p.M;
-  const size_t cnt[44] = {
+  const size_t cnt[kNConst] = {
       L * I, L * I, L * I, L * I,                 // from, to, slot_fr, slot_to
       L * D, L * D, L * D, L * D,                 // g, b, bh, smax
       (size_t)p.Lp * D, (size_t)p.Lp * D,         // ctg_smax, ctg_smax2
@@ -112,12 +114,14 @@ ConstLayout const_layout(const Problem& p) {
       G * M * D, G * M * D, G * M * D,            // seg_cost, seg_size, pcum
       T * N * D, T * N * D,                       // load_p, load_q
       T * D, T * D, T * D,                        // dt, rsv_req, sum_load
-      (size_t)p.N4 * p.Lp * D,                    // isft
-      (size_t)p.Lp * p.Np * D,                    // isf
-      (size_t)p.Lp * p.Kp * D};                   // lodf
+      (size_t)p.G4 * p.Lp * D,                    // isf_gT
+      (size_t)p.Lp * p.G16 * D,                   // isf_ga
+      (size_t)p.Lp * p.Kp * D,                    // lodf
+      T * (size_t)p.Lp * D,                       // cload
+      (size_t)p.Lp * D};                          // rsum
   ConstLayout c;
   size_t o = 0;
-  for (int i = 0; i < 44; ++i) {
+  for (int i = 0; i < kNConst; ++i) {
     o = (size_t)round_up((int64_t)o, kAlign);
     c.off[i] = o;
     o += cnt[i];
@@ -127,7 +131,7 @@ ConstLayout const_layout(const Problem& p) {
 }
 
 struct WorkLayout {
-  size_t off[32];
+  size_t off[40];
   size_t total;
 };
 
@@ -138,10 +142,11 @@ WorkLayout work_layout(const Problem& p) {
   const size_t nterm = (size_t)p.toff.total;
   const size_t cnt[] = {
       kParams * D, 8,                                   // params, step
+      (size_t)kSchedCap * kSchedStride * D,             // sched
       T * twoL * D, T * twoL * D,                       // epP, epQ
       9 * T * L * D,                                    // bco
       T * p.Lp * D,                                     // q2
-      (size_t)p.N4 * p.Tp * D,                          // pbarT
+      T * D,                                            // psum
       T * p.Lp * D, T * p.Kp * D,                       // F, Fk
       T * N * D, T * N * D,                             // lamp, lamq
       4 * T * G * D,                                    // gdev
@@ -150,11 +155,15 @@ WorkLayout work_layout(const Problem& p) {
       T * p.Kp * D, T * p.Kp * D,                       // smean, zval
       (size_t)p.Lp * p.Tp * D,                          // gfT
       T * p.Lp * D,                                     // qtot
-      T * p.Np * D,                                     // gpb
+      (size_t)p.nsplit * T * p.G16 * D,                 // gpdc
       T * twoL * D, T * twoL * D,                       // epGV, epGT
       nterm * D,                                        // tpart
       QG_NTERMS * D,                                    // terms
-      (size_t)p.n_x * D};                               // grad
+      T * D,                                            // drs
+      T * (size_t)p.nKc * D, T * (size_t)p.nKc * D,     // zmaxp, zargp
+      T * (size_t)p.nKc * D,                            // zsump
+      T * D,                                            // kstar
+      T * (size_t)p.nLc * D};                           // smaxp
   WorkLayout w;
   const int n = (int)(sizeof(cnt) / sizeof(cnt[0]));
   size_t o = 0;
@@ -168,6 +177,15 @@ WorkLayout work_layout(const Problem& p) {
 }
 
 }  // namespace
+
+int default_ctg_tc(int T, int lspan) {
+  // periods per block of the contingency map-reduce: enough blocks to give
+  // the chip several wavefronts per SIMD, within the LDS staging budget
+  const int cap = std::max(1, kCtgStageDoubles / (2 * lspan + kCtgLanes));
+  int tc = std::min(std::min(T, cap), kCtgMaxTc);
+  if (T > 8) tc = std::min(tc, (T + 2) / 3);
+  return std::max(1, tc);
+}
 
 qg_status fail(qg_status s, const std::string& msg) {
   g_err = msg;
@@ -247,15 +265,22 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   p->K = (int)p->ctg.size();
   p->Lp = (int)round_up(L, 64);
   p->Kp = (int)round_up(std::max(p->K, 1), 64);
-  p->Np = (int)round_up(N, 16);
-  p->N4 = (int)round_up(N, 4);
+  p->G16 = (int)round_up(G, 16);
+  p->G4 = (int)round_up(G, 4);
   p->Tp = (int)round_up(T, 16);
   p->n_x = 2LL * T * N + 4LL * T * G;
   p->flags = o->flags;
   p->nb_br = (int)((int64_t(T) * L + kBlock - 1) / kBlock);
   p->bus_chunks = (N + kBlock - 1) / kBlock;
   p->nb_bus = T * p->bus_chunks;
-  p->tile = CtgTile{8, 4};
+  p->nb_gen = (int)((int64_t(T) * G + kBlock - 1) / kBlock);
+  {
+    const int steps = p->Lp / 4;
+    p->nsplit = std::max(1, (steps + kAdjStepsPerBlock - 1) / kAdjStepsPerBlock);
+  }
+  p->nKc = p->Kp / kCtgLanes;
+  p->nLc = (p->Lp + kBlock - 1) / kBlock;
+  p->tile = CtgTile{8, 8, default_ctg_tc(T, 8 * 8)};
   p->nLb_max = p->Lp / 16;
   p->nKb_max = p->Kp / kCtgLanes;
   p->nLb = p->Lp / (p->tile.bl * p->tile.wl);
@@ -359,7 +384,8 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
                       HostBuild* hb) {
   (void)o;
   const int N = p->N, L = p->L, G = p->G, T = p->T, M = p->M, K = p->K;
-  const int Lp = p->Lp, Kp = p->Kp, Np = p->Np, N4 = p->N4;
+  const int Lp = p->Lp, Kp = p->Kp, G16 = p->G16, G4 = p->G4;
+  const int Np = (int)round_up(N, 16);  // row stride of the host ISF
   const ConstLayout cl = const_layout(*p);
   hb->const_bytes = cl.total;
   hb->image.assign(cl.total, 0);
@@ -465,7 +491,7 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
   Y.shrink_to_fit();
 
   // ---- injection shift factors: ISF[l][i] = y_l (Yinv[f][i] - Yinv[t][i])
-  std::vector<double> isf((size_t)Lp * Np, 0.0);
+  std::vector<double> isf((size_t)L * Np, 0.0);
   parallel_for(L, [&](int l) {
     const int a = red[d->br_from[l]], c = red[d->br_to[l]];
     double* row = &isf[(size_t)l * Np];
@@ -479,13 +505,40 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
   });
   Yinv.clear();
   Yinv.shrink_to_fit();
+  // ---- the ISF restricted to generator buses, its row sums and the load term:
+  // F_t = ISF p_bar_t = ISF[:, bus(j)] p_t - ISF load_t - mean_t ISF 1, and the
+  // slack-corrected injection gradient (eq. (correction)) of generator j is
+  // sum_l dL/dF_tl (ISF[l][bus(j)] - rsum_l / N).
   {
-    double* dst = reinterpret_cast<double*>(img.data() + cl.off[41]);  // isft [N4][Lp]
-    for (int l = 0; l < L; ++l)
-      for (int i = 0; i < N; ++i) dst[(size_t)i * Lp + l] = isf[(size_t)l * Np + i];
-    (void)N4;
+    std::vector<double> rsum(Lp, 0.0);
+    for (int l = 0; l < L; ++l) {
+      double s = 0.0;
+      for (int i = 0; i < N; ++i) s += isf[(size_t)l * Np + i];
+      rsum[l] = s;
+    }
+    double* gT = reinterpret_cast<double*>(img.data() + cl.off[41]);   // [G4][Lp]
+    double* ga = reinterpret_cast<double*>(img.data() + cl.off[42]);   // [Lp][G16]
+    for (int j = 0; j < G; ++j) {
+      const int bj = d->gen_bus[j];
+      for (int l = 0; l < L; ++l) {
+        const double v = isf[(size_t)l * Np + bj];
+        gT[(size_t)j * Lp + l] = v;
+        ga[(size_t)l * G16 + j] = v - rsum[l] / (double)N;
+      }
+    }
+    double* cl_ = reinterpret_cast<double*>(img.data() + cl.off[44]);  // [T][Lp]
+    parallel_for(T, [&](int t) {
+      const double* ld = d->load_p + (size_t)t * N;
+      for (int l = 0; l < L; ++l) {
+        const double* row = &isf[(size_t)l * Np];
+        double s = 0.0;
+        for (int i = 0; i < N; ++i) s += row[i] * ld[i];
+        cl_[(size_t)t * Lp + l] = s;
+      }
+    });
+    put(img, cl.off[45], rsum.data(), Lp);
+    (void)G4;
   }
-  put(img, cl.off[42], isf.data(), (size_t)Lp * Np);
 
   // ---- outage factors, NaN on the outaged branch itself and on padding
   {
@@ -515,7 +568,7 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
   // ---- scalars
   DevProblem& dp = p->dp;
   dp.N = N; dp.L = L; dp.G = G; dp.T = T; dp.M = M; dp.K = K;
-  dp.Lp = Lp; dp.Kp = Kp; dp.Np = Np; dp.N4 = N4; dp.Tp = p->Tp; dp.twoL = 2 * L;
+  dp.Lp = Lp; dp.Kp = Kp; dp.G16 = G16; dp.G4 = G4; dp.Tp = p->Tp; dp.twoL = 2 * L;
   dp.c_p = d->c_p; dp.c_q = d->c_q; dp.c_s = d->c_s; dp.c_ang = d->c_ang;
   dp.ang_max = d->ang_max; dp.c_rsv = d->c_rsv; dp.rho = d->rho; dp.vload = vload;
   return QG_OK;
@@ -537,7 +590,8 @@ void rebase_pointers(Problem* p, void* arena) {
   dp.u0 = D(28); dp.con = D(29); dp.csu = D(30); dp.csd = D(31); dp.cr = D(32);
   dp.seg_cost = D(33); dp.seg_size = D(34); dp.pcum = D(35);
   dp.load_p = D(36); dp.load_q = D(37); dp.dt = D(38); dp.rsv_req = D(39);
-  dp.sum_load = D(40); dp.isft = D(41); dp.isf = D(42); dp.lodf = D(43);
+  dp.sum_load = D(40); dp.isf_gT = D(41); dp.isf_ga = D(42); dp.lodf = D(43);
+  dp.cload = D(44); dp.rsum = D(45);
   p->arena = arena;
 }
 
@@ -548,11 +602,14 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   DevWork w;
   w.params = D(0);
   w.step = reinterpret_cast<int64_t*>(base + wl.off[1]);
-  w.epP = D(2); w.epQ = D(3); w.bco = D(4); w.q2 = D(5); w.pbarT = D(6);
-  w.F = D(7); w.Fk = D(8); w.lamp = D(9); w.lamq = D(10); w.gdev = D(11);
-  w.zpart = D(12); w.spart = D(13); w.rpart = D(14); w.qpart = D(15);
-  w.smean = D(16); w.zval = D(17); w.gfT = D(18); w.qtot = D(19); w.gpb = D(20);
-  w.epGV = D(21); w.epGT = D(22); w.tpart = D(23); w.terms = D(24); w.grad = D(25);
+  w.sched = D(2);
+  w.epP = D(3); w.epQ = D(4); w.bco = D(5); w.q2 = D(6); w.psum = D(7);
+  w.F = D(8); w.Fk = D(9); w.lamp = D(10); w.lamq = D(11); w.gdev = D(12);
+  w.zpart = D(13); w.spart = D(14); w.rpart = D(15); w.qpart = D(16);
+  w.smean = D(17); w.zval = D(18); w.gfT = D(19); w.qtot = D(20); w.gpdc = D(21);
+  w.epGV = D(22); w.epGT = D(23); w.tpart = D(24); w.terms = D(25);
+  w.drs = D(26); w.zmaxp = D(27); w.zargp = D(28); w.zsump = D(29); w.kstar = D(30);
+  w.smaxp = D(31);
   return w;
 }
 

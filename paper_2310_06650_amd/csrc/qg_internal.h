@@ -15,6 +15,11 @@ constexpr int kMaxT = 64;          // periods per problem (4 MFMA row tiles of 1
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kCtgLanes = 64;      // contingencies per wavefront in the map-reduce
 constexpr int kParams = 16;        // doubles in the per-step parameter block
+constexpr int kCtgStageDoubles = 5120;  // LDS staging budget of the contingency kernel
+constexpr int kCtgMaxTc = 8;            // periods per block of the contingency kernel
+constexpr int kAdjStepsPerBlock = 64;   // MFMA k-steps per block of the adjoint product
+constexpr int kSchedCap = 2048;         // solve steps per uploaded schedule table
+constexpr int kSchedStride = 16;        // doubles per step in the schedule table
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -23,8 +28,8 @@ struct DevProblem {
   int N, L, G, T, M, K;
   int Lp;    // L padded to 64 (row count of the outage-factor tile space)
   int Kp;    // K padded to 64 (one wavefront of contingencies)
-  int Np;    // N padded to 16 (MFMA output columns of the adjoint product)
-  int N4;    // N padded to 4  (MFMA reduction depth of the flow product)
+  int G16;   // G padded to 16 (MFMA output columns of the adjoint product)
+  int G4;    // G padded to 4  (MFMA reduction depth of the flow product)
   int Tp;    // T padded to 16 (MFMA rows)
   int twoL;  // endpoint slots per period
   // branches
@@ -47,22 +52,25 @@ struct DevProblem {
   // periods
   const double* load_p; const double* load_q;  // [T*N]
   const double* dt; const double* rsv_req; const double* sum_load;  // [T]
-  // sensitivities
-  const double* isft;   // [N4][Lp]   ISF transposed, zero padded
-  const double* isf;    // [Lp][Np]   ISF, zero padded
-  const double* lodf;   // [Lp][Kp]   outage factors; NaN marks (k,k) and padding
+  // sensitivities, restricted to generator buses
+  const double* isf_gT;  // [G4][Lp]  ISF[l][bus(j)], zero padded (B of the flow product)
+  const double* isf_ga;  // [Lp][G16] ISF[l][bus(j)] - rsum[l]/N (B of the adjoint product)
+  const double* cload;   // [T][Lp]   sum_i ISF[l][i] load_p[t][i]
+  const double* rsum;    // [Lp]      sum_i ISF[l][i]
+  const double* lodf;    // [Lp][Kp]  outage factors; NaN marks (k,k) and padding
   // prices
   double c_p, c_q, c_s, c_ang, ang_max, c_rsv, rho, vload;
 };
 
 // Device view of the caller's workspace.
 struct DevWork {
-  double* params;      // [kParams]
-  int64_t* step;       // [1] Adam iteration counter used by qg_solve
+  double* params;      // [kParams] parameters of the step being evaluated
+  int64_t* step;       // [1] index of the current step in the schedule table
+  double* sched;       // [kSchedCap][kSchedStride] per-step eps, beta, rho_s, alpha[6], bc1, bc2
   double* epP; double* epQ;      // [T][2L] branch flows at bus-sorted endpoint slots
   double* bco;         // [9][T][L] per-branch reverse coefficients
   double* q2;          // [T][Lp]  max(q_fr^2, q_to^2)
-  double* pbarT;       // [N4][Tp] balanced injections, transposed
+  double* psum;        // [T]      sum_j p_tj
   double* F;           // [T][Lp]  base-case DC flows
   double* Fk;          // [T][Kp]  flows of the outaged branches
   double* lamp; double* lamq;    // [T][N] balance multipliers
@@ -73,11 +81,16 @@ struct DevWork {
   double* zval;        // [T][Kp]
   double* gfT;         // [Lp][Tp] dL/dF, transposed
   double* qtot;        // [T][Lp]  dL/d qmax2
-  double* gpb;         // [T][Np]  dL/d p_bar
+  double* gpdc;        // [nsplit][T][G16] DC part of dL/dp (split-K partials)
   double* epGV; double* epGT;    // [T][2L] endpoint adjoints
   double* tpart;       // term partial sums
   double* terms;       // [QG_NTERMS] last evaluated terms
-  double* grad;        // [n_x] gradient scratch for qg_solve's eager path
+  double* drs;         // [T]       reserve-shortfall derivative, subtracted from dL/dr
+  double* zmaxp;       // [T][nKc]  per-chunk worst penalty
+  double* zargp;       // [T][nKc]  its contingency index
+  double* zsump;       // [T][nKc]  per-chunk penalty sum
+  double* kstar;       // [T]       worst contingency of the period
+  double* smaxp;       // [T][nLc]  per-chunk dL/dF of the worst contingency's own branch
 };
 
 // Offsets of the term partial sums inside DevWork::tpart.
@@ -89,6 +102,7 @@ struct TermOffsets {
 struct CtgTile {
   int bl;   // branches per wavefront (8, 16 or 32)
   int wl;   // wavefronts per block, stacked along branches
+  int tc;   // periods per block (the period range is split over grid.z)
 };
 
 // Homotopy source of one evaluation.
@@ -106,7 +120,7 @@ struct EvalMode {
 struct Problem {
   // sizes
   int N, L, G, T, M, K;
-  int Lp, Kp, Np, N4, Tp;
+  int Lp, Kp, G16, G4, Tp;
   int64_t n_x;
   uint32_t flags;
   std::vector<int32_t> ctg;
@@ -114,6 +128,9 @@ struct Problem {
   int nb_br;      // blocks of the per-(t, branch) kernels
   int nb_bus;     // blocks of the per-(t, bus chunk) kernels
   int bus_chunks; // bus chunks per period
+  int nb_gen;     // blocks of the per-(t, generator) final stage
+  int nsplit;     // reduction splits of the adjoint product
+  int nKc, nLc;   // chunks of Kp (64 wide) and Lp (256 wide)
   CtgTile tile;
   int nLb, nKb;   // partial counts of the contingency map-reduce
   int nLb_max, nKb_max;
@@ -139,19 +156,17 @@ qg_status fail(qg_status s, const std::string& msg);
 
 // Validate the description and find the contingency set.  Fills p's sizes.
 qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p);
-// Factor, sensitivities and the arena image; sets offsets in p->dp relative
-// to arena base (as byte offsets cast to pointers) -- rebased on upload.
+// Factor, sensitivities and the arena image.
 qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
                       HostBuild* hb);
 void rebase_pointers(Problem* p, void* arena);
 DevWork carve_workspace(const Problem* p, void* ws);
-
-
+int default_ctg_tc(int T, int lspan);
 
 // Kernel launchers (qg_kernels.hip).
 int launch_eval(const Problem* p, const DevWork& w, const double* x, double* grad,
                 double* terms_out, const EvalMode& mode, int fuse_adam, double* m,
-                double* v, void* stream, void** events /* nullable [2*QG_NKERNELS] */);
+                double* v, void* stream, void** events /* nullable [QG_NKERNELS] */);
 int launch_adam(const Problem* p, double* x, double* m, double* v, const double* g,
                 const double lr[QG_NCLASS], double bc1, double bc2, double b1,
                 double b2, double eps, int eps_in_num, void* stream);

@@ -1,22 +1,23 @@
 // HIP kernels of one solver step for gfx950 (MI355X).
 //
 // Stage map (one launch each, in stream order):
-//   k_forward       per-(t, branch) AC flows and penalties        (Section II-B Ex. 1, 4; II-G)
-//                   + one block per period for device terms and   (Ex. 2, 3; eq. (nlp_updated))
-//                     the slack-balanced DC injections            (Section II-E)
-//   k_balance_flow  per-(t, bus) power balance from bus-sorted    (Ex. 4)
-//                     endpoint flows (LDS-staged segmented sums)
-//                   + base-case DC flows F = Pbar ISF^T on MFMA   (eqs. (Yb_solve)-(p_flow))
-//   k_ctg_main      per-(t, l, k) outage flows F_l + LODF_lk F_k,  (eqs. (rank_correct),
-//                     penalties and their partial reductions        (sfr_pen)-(zctg), (2nd_lin_sys))
-//   k_ctg_finalize  per period: worst + mean aggregation, weights, the
-//                     adjoint of the flows dL/dF
-//   k_adjoint       dL/dPbar = (dL/dF) ISF on MFMA                (eqs. (2nd_lin_sys), (correction))
+//   k_forward       per-(t, branch) AC flows and penalties          (Section II-B Ex. 1, 4; II-G)
+//                   + one block per period: device terms, reserve     (Ex. 2, 3; eq. (nlp_updated))
+//                     shortfall and the period's total output
+//   k_balance_flow  per-(t, bus) power balance from bus-sorted endpoint flows
+//                     (LDS-staged segmented sums)                      (Ex. 4)
+//                   + base-case DC flows on FP64 MFMA:                 (eqs. (Yb_solve)-(p_flow))
+//                     F_t = ISF[:, gen] p_t - ISF load_t - mean_t ISF 1 (uniform slack)
+//   k_ctg_main      per-(t, l, k) outage flows F_l + LODF_lk F_k, their (eqs. (rank_correct),
+//                     penalties and partial reductions                   (sfr_pen)-(zctg), (2nd_lin_sys))
+//   k_ctg_zred      per-(t, k) penalties z_tk, per-chunk worst and sum
+//   k_ctg_asm       per-(t, l) dL/dF and dL/dqmax2 (mean + worst-contingency weights)
+//   k_adjoint       dL/dp_tj (DC part) = sum_l dL/dF_tl (ISF[l][bus(j)] - rowsum_l/N)
+//                     on FP64 MFMA, split over the branch dimension      (eqs. (2nd_lin_sys), (correction))
 //                   + per-(t, branch) reverse of the AC flows into bus-sorted endpoint slots
-//   k_final         per-(t, bus) segmented sums of endpoint adjoints, per-generator
-//                     gradient assembly (uniform-slack correction, eq. (correction)),
-//                     then either the gradient or the fused Adam update with clip (Alg. 3),
-//                     and the deterministic sum of the objective terms.
+//   k_final         per-(t, bus) segmented sums of endpoint adjoints and per-(t, generator)
+//                     gradient assembly, then either the gradient or the fused Adam
+//                     update with clip (Alg. 3), and the deterministic sum of the terms.
 //
 // Every reduction has a fixed order (no floating-point atomics), so a step is
 // bitwise reproducible run to run.
@@ -50,7 +51,8 @@ struct EvalArgs {
   double* v;
   EvalMode mode;
   int fuse_adam;
-  int nb_br, nb_bus, bus_chunks, nLb, nKb;
+  int nb_br, nb_bus, bus_chunks, nb_gen, nsplit;
+  int nLb, nKb, nKc, nLc, tc;
   TermOffsets toff;
 };
 
@@ -74,10 +76,20 @@ __device__ __forceinline__ double soft_abs_d(double v, double eps) {
   return s > 0.0 ? v / s : 0.0;
 }
 
-template <int CTRL>
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps on
+// y^-2 = x (y <- y + y (1 - x y^2) / 2), which restores FP64 accuracy.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double r = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, r, y);
+  r = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, r, y);
+}
+
+template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -87,51 +99,108 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wavefront (all lanes active).  Butterflies
-// inside each row of 16 lanes with DPP (quad swaps, half-row and row
-// mirrors), then the four row sums in lane order.  Every lane gets the same
-// bits.
+// Sum over the 64 lanes of a wavefront (all lanes active), returned in every
+// lane.  Butterflies inside each row of 16 lanes (quad swaps, half-row and
+// row mirrors) give every lane its row sum; row_bcast15 then adds row 0's
+// sum into row 1 and row 2's into row 3, and row_bcast31 adds rows 0+1 into
+// row 3, so lane 63 holds ((r0 + r1) + (r2 + r3)).
 __device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) +
-         readlane_f64(v, 48);
+  v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);   // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
+  return readlane_f64(v, 63);
 }
 
-// Deterministic block sum of NV values over a 256-thread block; every
-// thread returns the totals.  lds holds NV*256 doubles.
+// Largest value over the 64 lanes of a wavefront, ties to the smaller index
+// (a total order, so the combination order does not matter); every lane gets
+// the winner.  Entries with index INT_MAX are empty.
+__device__ __forceinline__ bool better(double v2, int i2, double v, int i) {
+  if (i2 == INT_MAX) return false;
+  if (i == INT_MAX) return true;
+  return v2 > v || (v2 == v && i2 < i);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+  const double v2 = dpp_f64<CTRL, 0xF>(v);
+  const int i2 = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  if (better(v2, i2, v, i)) { v = v2; i = i2; }
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  argmax_step<0xB1>(v, i);
+  argmax_step<0x4E>(v, i);
+  argmax_step<0x141>(v, i);
+  argmax_step<0x140>(v, i);
+  // every lane of a row holds the row's winner; combine rows 0..3 in order
+  double bv = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+  for (int r = 16; r < 64; r += 16) {
+    const double v2 = readlane_f64(v, r);
+    const int i2 = __builtin_amdgcn_readlane(i, r);
+    if (better(v2, i2, bv, bi)) { bv = v2; bi = i2; }
+  }
+  v = bv;
+  i = bi;
+}
+
+// Deterministic block sum of NV values; every thread returns the totals.
+// Each wavefront reduces with DPP, then the per-wavefront sums are added in
+// wavefront order.  lds holds NV * 16 doubles; ends with a barrier so that
+// lds can be reused.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) lds[q * kBlock + tid] = v[q];
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-#pragma unroll
-      for (int q = 0; q < NV; ++q) lds[q * kBlock + tid] += lds[q * kBlock + tid + s];
-    }
-    __syncthreads();
+  for (int q = 0; q < NV; ++q) {
+    const double ws = wave_sum(v[q]);
+    if (lane == 0) lds[q * 16 + wv] = ws;
   }
+  __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NV; ++q) v[q] = lds[q * kBlock];
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[q * 16 + w];
+    v[q] = s;
+  }
   __syncthreads();
 }
 
-__device__ double sched_scale(double i, double n) {
-  const double th = 2.0 * i / n - 1.0;
-  const double e = exp(4.0 * th);
-  return e / (0.6 + e);
+// Block argmax (ties to the smaller index); lds holds 16 doubles and 16 ints.
+__device__ __forceinline__ void block_argmax(double& v, int& i, double* ldsv, int* ldsi) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  wave_argmax(v, i);
+  if (lane == 0) { ldsv[wv] = v; ldsi[wv] = i; }
+  __syncthreads();
+  double bv = ldsv[0];
+  int bi = ldsi[0];
+  for (int w = 1; w < nw; ++w)
+    if (better(ldsv[w], ldsi[w], bv, bi)) { bv = ldsv[w]; bi = ldsi[w]; }
+  v = bv;
+  i = bi;
+  __syncthreads();
 }
 
-__device__ double sched_log(double a0, double af, double s) {
-  return a0 * pow(10.0, s * log10(af / a0));
+// sum_{q < n} src[q * stride] in ascending q, with up to U loads in flight.
+template <int U>
+__device__ __forceinline__ double strided_sum(const double* src, int n, size_t stride) {
+  double acc = 0.0;
+  for (int q0 = 0; q0 < n; q0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = (q0 + u < n) ? src[(size_t)(q0 + u) * stride] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
+  }
+  return acc;
 }
 
-// Homotopy and step sizes of this step: from the arguments, or from the
-// iteration-indexed schedule of the solve loop (eqs. (norm_t)-(step_size)).
+// Homotopy and step sizes of this step: from the arguments, or from the row
+// of the schedule table (eqs. (norm_t)-(step_size), evaluated on the host per
+// iteration) that the step counter points at.
 __device__ void resolve_params(const EvalArgs& a, StepParams& sp) {
   if (a.mode.schedule == 0) {
     sp.eps = a.mode.eps;
@@ -141,15 +210,33 @@ __device__ void resolve_params(const EvalArgs& a, StepParams& sp) {
     sp.bc1 = sp.bc2 = 1.0;
     return;
   }
-  const double i = (double)(a.w.step[0] + 1);
-  const double n = (double)a.mode.n_total;
-  const double s = sched_scale(i, n);
-  sp.eps = sched_log(a.mode.eps0, a.mode.epsf, s);
-  sp.beta = a.mode.beta0 + (a.mode.betaf - a.mode.beta0) * (i / n);
-  sp.rho_s = a.mode.rho0 + (a.mode.rhof - a.mode.rho0) * (i / n);
-  for (int c = 0; c < QG_NCLASS; ++c) sp.alpha[c] = sched_log(a.mode.alpha0[c], a.mode.alphaf[c], s);
-  sp.bc1 = 1.0 - pow(a.mode.adam_b1, i);
-  sp.bc2 = 1.0 - pow(a.mode.adam_b2, i);
+  const double* row = a.w.sched + (size_t)a.w.step[0] * kSchedStride;
+  sp.eps = row[0];
+  sp.beta = row[1];
+  sp.rho_s = row[2];
+  for (int c = 0; c < QG_NCLASS; ++c) sp.alpha[c] = row[3 + c];
+  sp.bc1 = row[9];
+  sp.bc2 = row[10];
+}
+
+// Contribution of one overloaded outage element: with s = sqrt(s2),
+// e = s - s_ctg and sigma = sqrt(max(e,0)^2 + eps^2), returns sigma - eps (the
+// penalty above its floor), and dC/dP, dC/dqmax2 scaled by kt.
+__device__ __forceinline__ double ctg_overload(double P, double s2, double smx, double eps,
+                                               double eps2, double kt, double& dP, double& dq) {
+  const double rs = rsqrt_nr(s2);
+  const double s = s2 * rs;
+  const double em = fmax(s - smx, 0.0);
+  const double w2 = fma(em, em, eps2);
+  dP = 0.0;
+  dq = 0.0;
+  if (!(w2 > 0.0)) return 0.0;
+  const double rw = rsqrt_nr(w2);
+  const double sig = w2 * rw;
+  const double gs = kt * em * rw;
+  dP = gs * P * rs;
+  dq = 0.5 * gs * rs;
+  return sig - eps;
 }
 
 // ---------------------------------------------------------------------------
@@ -187,33 +274,49 @@ __device__ __forceinline__ void bus_segsum(const double* const (&src)[NV], const
 
 // ---------------------------------------------------------------------------
 // FP64 MFMA slab product.  A 256-thread block computes the 16 output columns
-// [n0, n0+16) of C = A * B for all MT*16 rows, where A is stored transposed
-// (AT[k][row], row stride Tp) and B row-major (ldb).  The reduction depth kd
-// (a multiple of 4) is split over the four wavefronts; their partial tiles
-// are summed in LDS in wavefront order.  v_mfma_f64_16x16x4f64 operands:
-// lane l holds A[l%16][l/16] and B[l/16][l%16]; the result D[l/16 + 4r][l%16]
-// sits in register r of lane l.
-template <int MT, class Epi>
-__device__ __forceinline__ void mfma_slab(const double* __restrict__ AT, int Tp,
-                                          const double* __restrict__ B, int ldb, int kd,
-                                          int n0, double* lds, Epi epi) {
+// [n0, n0+16) of C = A * B over the reduction range [k0, k1) (multiples of 4)
+// for all MT*16 rows; aload(k, row) supplies A[row][k] (zero outside A) and B
+// is row-major (ldb).  The range is split over the four wavefronts; operands
+// of 8 consecutive k-steps are loaded before their MFMAs so that their memory
+// latencies overlap.  The partial tiles are summed in LDS in wavefront order.
+// v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; the result D[l/16 + 4r][l%16] sits in register r of lane l.
+constexpr int kSlabBatch = 8;
+
+template <int MT, class ALoad, class Epi>
+__device__ __forceinline__ void mfma_slab(ALoad aload, const double* __restrict__ B, int ldb,
+                                          int k0, int k1, int n0, double* lds, Epi epi) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int steps = kd >> 2;
+  const int steps = (k1 - k0) >> 2;
   const int s0 = (steps * wv) >> 2, s1 = (steps * (wv + 1)) >> 2;
   v4d acc[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
   const int kr = lane >> 4, cc = lane & 15;
-  for (int st = s0; st < s1; ++st) {
-    const int k = st * 4 + kr;
+  int st = s0;
+  for (; st + kSlabBatch <= s1; st += kSlabBatch) {
+    double bb[kSlabBatch], aa[kSlabBatch][MT];
+#pragma unroll
+    for (int u = 0; u < kSlabBatch; ++u) {
+      const int k = k0 + (st + u) * 4 + kr;
+      bb[u] = B[(size_t)k * ldb + n0 + cc];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) aa[u][mt] = aload(k, mt * 16 + cc);
+    }
+#pragma unroll
+    for (int u = 0; u < kSlabBatch; ++u)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[u][mt], bb[u], acc[mt], 0, 0, 0);
+  }
+  for (; st < s1; ++st) {
+    const int k = k0 + st * 4 + kr;
     const double b = B[(size_t)k * ldb + n0 + cc];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const double av = AT[(size_t)k * Tp + mt * 16 + cc];
-      acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[mt], 0, 0, 0);
-    }
+    for (int mt = 0; mt < MT; ++mt)
+      acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aload(k, mt * 16 + cc), b, acc[mt], 0, 0, 0);
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -232,26 +335,26 @@ __device__ __forceinline__ void mfma_slab(const double* __restrict__ AT, int Tp,
   __syncthreads();
 }
 
-template <class Epi>
-__device__ __forceinline__ void mfma_slab_dispatch(int mtiles, const double* AT, int Tp,
-                                                   const double* B, int ldb, int kd, int n0,
-                                                   double* lds, Epi epi) {
+template <class ALoad, class Epi>
+__device__ __forceinline__ void mfma_slab_dispatch(int mtiles, ALoad aload, const double* B,
+                                                   int ldb, int k0, int k1, int n0, double* lds,
+                                                   Epi epi) {
   switch (mtiles) {
-    case 1: mfma_slab<1>(AT, Tp, B, ldb, kd, n0, lds, epi); break;
-    case 2: mfma_slab<2>(AT, Tp, B, ldb, kd, n0, lds, epi); break;
-    case 3: mfma_slab<3>(AT, Tp, B, ldb, kd, n0, lds, epi); break;
-    default: mfma_slab<4>(AT, Tp, B, ldb, kd, n0, lds, epi); break;
+    case 1: mfma_slab<1>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    case 2: mfma_slab<2>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    case 3: mfma_slab<3>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    default: mfma_slab<4>(aload, B, ldb, k0, k1, n0, lds, epi); break;
   }
 }
 
 // ---------------------------------------------------------------------------
-// K1: branch forward + period blocks
+// K1: branch forward, device blocks, injection blocks
 
-__device__ void branch_forward(const EvalArgs& a, const StepParams& sp, double* lds) {
+__device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk, double* lds) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int T = p.T, L = p.L, N = p.N;
-  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  const int idx = blk * kBlock + threadIdx.x;
   double part[2] = {0.0, 0.0};
   if (idx < T * L) {
     const int t = idx / L, l = idx - t * L;
@@ -309,14 +412,18 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, double* 
   }
   block_sum<2>(part, lds);
   if (threadIdx.x == 0) {
-    w.tpart[a.toff.br + blockIdx.x] = part[0];
-    w.tpart[a.toff.ang + blockIdx.x] = part[1];
+    w.tpart[a.toff.br + blk] = part[0];
+    w.tpart[a.toff.ang + blk] = part[1];
   }
 }
 
-// One block per period t: device costs and penalised device constraints
-// (Examples 2-3, eq. (nlp_updated)), reserve shortfall, device-only partials,
-// and the uniform-slack DC injections (Section II-E, eq. (correction)).
+// One block per period t, one thread per generator (looping when G > 256):
+// block-bid cost, no-load, start-up/shut-down and reserve costs (Examples
+// 2-3), the penalised device constraints of eq. (nlp_updated) and their
+// partials.  The next period's terms that depend on this period's p and u
+// are included, so each thread writes only its own partials.  The block also
+// sums the period's output (for the uniform slack of the DC flows) and
+// reserve (for the shortfall penalty), and zeroes the padding read later.
 __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, double* lds) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
@@ -346,8 +453,8 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
       lo = p.pcum[j * M + m];
     }
     const double du = uj - um1;
-    double dev = dtt * cost + dtt * p.con[j] * uj + p.csu[j] * fmax(du, 0.0) +
-                 p.csd[j] * fmax(-du, 0.0) + dtt * p.cr[j] * rj;
+    const double dev = dtt * cost + dtt * p.con[j] * uj + p.csu[j] * fmax(du, 0.0) +
+                       p.csd[j] * fmax(-du, 0.0) + dtt * p.cr[j] * rj;
     double gp = dtt * dcost;
     double gu = dtt * p.con[j] + (du > 0.0 ? p.csu[j] : 0.0) - (-du > 0.0 ? p.csd[j] : 0.0);
     double gr = dtt * p.cr[j];
@@ -356,7 +463,6 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
       const double du1 = xU[e + G] - uj;
       gu -= (du1 > 0.0 ? p.csu[j] : 0.0) - (-du1 > 0.0 ? p.csd[j] : 0.0);
     }
-    // penalised device constraints at t
     double pen = 0.0, a_, dd;
     a_ = pj + rj - p.pmax[j] * uj;                        // headroom
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
@@ -379,8 +485,7 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
     a_ = rj - p.rmax[j] * uj;                             // reserve capability
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
     gr += dd; gu -= dd * p.rmax[j];
-    // the next period's ramp constraints depend on p_t
-    if (t + 1 < T) {
+    if (t + 1 < T) {  // the next period's ramp constraints depend on p_t
       const double dt1 = p.dt[t + 1];
       const double k1 = sp.rho_s * p.rho * sp.beta * dt1;
       const double p1 = xP[e + G], u1 = xU[e + G];
@@ -399,42 +504,17 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
     acc[3] += rj;
   }
   block_sum<4>(acc, lds);
-  // zonal reserve shortfall
   const double short_ = p.rsv_req[t] - acc[3];
   const double krs = dtt * p.c_rsv * sp.beta;
-  const double drs = krs * soft_relu_d(short_, eps);
-  if (drs != 0.0)
-    for (int j = tid; j < G; j += kBlock) w.gdev[2 * TG + (size_t)t * G + j] -= drs;
   if (tid == 0) {
     w.tpart[a.toff.dev + t] = acc[0];
     w.tpart[a.toff.pen + t] = acc[1];
     w.tpart[a.toff.rsv + t] = krs * soft_relu(short_, eps);
+    w.drs[t] = krs * soft_relu_d(short_, eps);
+    w.psum[t] = acc[2];
   }
-  // uniform-slack DC injections, written transposed for the MFMA A operand
-  const double mean = (acc[2] - p.sum_load[t]) / (double)N;
-  for (int i = tid; i < p.N4; i += kBlock) {
-    double v = 0.0;
-    if (i < N) {
-      double s = 0.0;
-      for (int g = p.gptr[i]; g < p.gptr[i + 1]; ++g) s += xP[(size_t)t * G + p.glist[g]];
-      v = (s - p.load_p[(size_t)t * N + i]) - mean;
-    }
-    w.pbarT[(size_t)i * p.Tp + t] = v;
-  }
-  // zero the padding read by later stages
   for (int l = p.L + tid; l < p.Lp; l += kBlock) w.q2[(size_t)t * p.Lp + l] = 0.0;
   for (int k = p.K + tid; k < p.Kp; k += kBlock) w.Fk[(size_t)t * p.Kp + k] = 0.0;
-  if (t == 0) {
-    const int padc = p.Tp - T;
-    for (int e = tid; e < p.N4 * padc; e += kBlock) {
-      const int i = e / padc, c = T + e % padc;
-      w.pbarT[(size_t)i * p.Tp + c] = 0.0;
-    }
-    for (int e = tid; e < p.Lp * padc; e += kBlock) {
-      const int l = e / padc, c = T + e % padc;
-      w.gfT[(size_t)l * p.Tp + c] = 0.0;
-    }
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
@@ -451,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
     pb[PB_BC2] = sp.bc2;
   }
   if ((int)blockIdx.x < a.nb_br)
-    branch_forward(a, sp, lds);
+    branch_forward(a, sp, blockIdx.x, lds);
   else
     period_block(a, sp, blockIdx.x - a.nb_br, lds);
 }
@@ -501,38 +581,54 @@ __global__ __launch_bounds__(kBlock) void k_balance_flow(EvalArgs a) {
     if (tid == 0) w.tpart[a.toff.bal + blockIdx.x] = part[0];
     return;
   }
-  // F[t][l] = sum_i Pbar[t][i] ISF[l][i]; also the outaged branches' flows
+  // F[t][l] = sum_j p_tj ISF[l][bus(j)] - ISF load_t - mean_t rowsum_l, with
+  // mean_t = (sum_j p_tj - sum_i load_ti) / N the uniform slack; also the
+  // outaged branches' flows
   const int slab = blockIdx.x - a.nb_bus;
   const int n0 = slab * 16;
   double* F = w.F;
   double* Fk = w.Fk;
-  const int T = p.T, Lp = p.Lp, Kp = p.Kp;
+  const int T = p.T, G = p.G, Lp = p.Lp, Kp = p.Kp, N = p.N;
   const int* kof = p.kof;
+  const double* xP = a.x + 2 * (size_t)T * N;
+  const double* cload = p.cload;
+  const double* rsum = p.rsum;
+  const double* psum = w.psum;
+  const double* sum_load = p.sum_load;
+  auto aload = [=](int k, int row) -> double {
+    return (row < T && k < G) ? xP[(size_t)row * G + k] : 0.0;
+  };
   auto epi = [=](int row, int col, double v) {
     if (row < T) {
-      F[(size_t)row * Lp + col] = v;
+      const double mean = (psum[row] - sum_load[row]) / (double)N;
+      const double f = (v - cload[(size_t)row * Lp + col]) - mean * rsum[col];
+      F[(size_t)row * Lp + col] = f;
       const int k = kof[col];
-      if (k >= 0) Fk[(size_t)row * Kp + k] = v;
+      if (k >= 0) Fk[(size_t)row * Kp + k] = f;
     }
   };
-  mfma_slab_dispatch(p.Tp / 16, w.pbarT, p.Tp, p.isft, Lp, p.N4, n0, smem, epi);
+  mfma_slab_dispatch(p.Tp / 16, aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
 }
 
 // ---------------------------------------------------------------------------
 // K3: contingency map-reduce over (t, l, k).
 //
 // A wavefront owns 64 contingencies (one per lane) and BL consecutive
-// branches; its BL outage factors stay in registers for all T periods.  For
-// each (t, l) every lane forms the post-outage flow P = F_tl + LODF_lk F_tk
-// and tests P^2 + qmax2_tl > s_ctg^2.  Only when some lane of the wavefront
-// is overloaded does it compute the soft-ReLU, its derivative and the
+// branches; its BL outage factors stay in registers.  A block stacks WL
+// wavefronts along l and covers the periods [t0, t0 + TC) (grid.z splits
+// the periods); its base flows F, reactive maxima qmax2 and the flows of its
+// 64 outaged branches are staged in LDS once.  For each (t, l) every lane
+// forms the post-outage flow P = F_tl + LODF_lk F_tk and tests
+// P^2 + qmax2_tl > s_ctg^2.  Only when some lane of the wavefront is
+// overloaded does it evaluate the soft-ReLU and its derivative and take the
 // wavefront sums over k (R: d/dF_tl, Q: d/dqmax2_tl); z_tk and S_tk (the
-// derivative through F_tk) accumulate in the lane over l.  The outaged branch
-// itself and the padding carry a NaN factor, so they never test overloaded.
-// Blocks stack WL wavefronts along l; their z and S are summed in LDS.
+// derivative through F_tk) accumulate in the lane over l and are summed over
+// the block's wavefronts in LDS.  The outaged branch itself and the padding
+// carry a NaN factor, so they never test overloaded.
 
 template <int BL>
 __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
+  extern __shared__ double dyn[];
   __shared__ double zsh[2][8][64];
   __shared__ double ssh[2][8][64];
   const DevProblem& p = a.p;
@@ -540,11 +636,34 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int WL = blockDim.x >> 6;
+  const int lspan = BL * WL;
   const int lb = blockIdx.x, kb = blockIdx.y;
-  const int lbase = __builtin_amdgcn_readfirstlane(lb * BL * WL + wv * BL);
-  const bool on = lbase < p.Lp;
-  const int k = kb * 64 + lane;
   const int T = p.T, Lp = p.Lp, Kp = p.Kp;
+  const int TC = a.tc;
+  const int t0 = blockIdx.z * TC;
+  const int nt = min(TC, T - t0);
+  const int lblk = lb * lspan;
+  const int lbase = __builtin_amdgcn_readfirstlane(lblk + wv * BL);
+  const bool on = lbase < Lp;
+  const int k = kb * 64 + lane;
+  // stage sFQ[t][l][2] = {F, qmax2} and sFk[t][64]
+  double* sFQ = dyn;
+  double* sFk = dyn + 2 * TC * lspan;
+  for (int e = threadIdx.x; e < nt * lspan; e += blockDim.x) {
+    const int tt = e / lspan, ll = e - tt * lspan;
+    const int l = lblk + ll;
+    double f = 0.0, q = 0.0;
+    if (l < Lp) {
+      f = w.F[(size_t)(t0 + tt) * Lp + l];
+      q = w.q2[(size_t)(t0 + tt) * Lp + l];
+    }
+    sFQ[2 * e] = f;
+    sFQ[2 * e + 1] = q;
+  }
+  for (int e = threadIdx.x; e < nt * 64; e += blockDim.x) {
+    const int tt = e >> 6, kk = e & 63;
+    sFk[e] = w.Fk[(size_t)(t0 + tt) * Kp + kb * 64 + kk];
+  }
   const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
   const double eps2 = eps * eps;
   double lod[BL], smx[BL], smx2[BL];
@@ -556,32 +675,32 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
       smx2[j] = p.ctg_smax2[lbase + j];
     }
   }
-  for (int t = 0; t < T; ++t) {
+  __syncthreads();
+  // per-period z and S of this lane, kept in registers until every period is
+  // done (selects keep the arrays in registers with a rolled loop)
+  double zs[kCtgMaxTc], ss[kCtgMaxTc];
+#pragma unroll
+  for (int u = 0; u < kCtgMaxTc; ++u) { zs[u] = 0.0; ss[u] = 0.0; }
+  for (int tt = 0; tt < nt; ++tt) {
+    const int t = t0 + tt;
     double zacc = 0.0, sacc = 0.0, racc = 0.0, qacc = 0.0;
     if (on) {
       const double kt = p.dt[t] * p.c_s * beta;
-      const double fk = w.Fk[(size_t)t * Kp + k];
-      const double* Ft = w.F + (size_t)t * Lp + lbase;
-      const double* Qt = w.q2 + (size_t)t * Lp + lbase;
+      const double fk = sFk[tt * 64 + lane];
+      const double* fq = sFQ + 2 * (tt * lspan + wv * BL);
+      double Fv[BL], Qv[BL];
+#pragma unroll
+      for (int j = 0; j < BL; ++j) { Fv[j] = fq[2 * j]; Qv[j] = fq[2 * j + 1]; }
 #pragma unroll
       for (int j = 0; j < BL; ++j) {
-        const double P = fma(lod[j], fk, Ft[j]);
-        const double s2 = fma(P, P, Qt[j]);
+        const double P = fma(lod[j], fk, Fv[j]);
+        const double s2 = fma(P, P, Qv[j]);
         const bool over = s2 > smx2[j];
         if (__builtin_amdgcn_ballot_w64(over)) {
           double dP = 0.0, dq = 0.0;
           if (over) {
-            const double s = sqrt(s2);
-            const double em = fmax(s - smx[j], 0.0);
-            const double sig = sqrt(em * em + eps2);
-            if (sig > 0.0) {
-              zacc += em * em / (sig + eps);
-              const double gs = kt * em / sig;
-              const double inv_s = 1.0 / s;
-              dP = gs * P * inv_s;
-              dq = 0.5 * gs * inv_s;
-              sacc += lod[j] * dP;
-            }
+            zacc += ctg_overload(P, s2, smx[j], eps, eps2, kt, dP, dq);
+            sacc += lod[j] * dP;
           }
           const double rs = wave_sum(dP);
           const double qs = wave_sum(dq);
@@ -594,122 +713,153 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
         w.qpart[o] = qacc;
       }
     }
-    const int par = t & 1;
-    zsh[par][wv][lane] = zacc;
-    ssh[par][wv][lane] = sacc;
-    __syncthreads();
-    if (wv == 0) {
-      double z = 0.0, s = 0.0;
-      for (int q = 0; q < WL; ++q) { z += zsh[par][q][lane]; s += ssh[par][q][lane]; }
-      const size_t o = ((size_t)lb * T + t) * Kp + k;
-      w.zpart[o] = z;
-      w.spart[o] = s;
+#pragma unroll
+    for (int u = 0; u < kCtgMaxTc; ++u)
+      if (u == tt) { zs[u] = zacc; ss[u] = sacc; }
+  }
+  // sum z and S over the block's wavefronts, one period at a time
+#pragma unroll
+  for (int u = 0; u < kCtgMaxTc; ++u) {
+    if (u < nt) {
+      const int par = u & 1;
+      zsh[par][wv][lane] = zs[u];
+      ssh[par][wv][lane] = ss[u];
+      __syncthreads();
+      if (wv == 0) {
+        double z = 0.0, s2 = 0.0;
+        for (int q = 0; q < WL; ++q) { z += zsh[par][q][lane]; s2 += ssh[par][q][lane]; }
+        const size_t o = ((size_t)lb * T + t0 + u) * Kp + k;
+        w.zpart[o] = z;
+        w.spart[o] = s2;
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// K4: per-period aggregation over contingencies (worst + mean, Table 1 rows),
-// the worst contingency's own column, and dL/dF, dL/dqmax2.
+// K4: per-(t, k) penalties z_tk (the l-block partials plus the floor
+// (L-1) eps), the mean outage-correction derivative, and per 64-contingency
+// chunk the worst penalty (smallest index on ties) and the sum.  One 64-thread
+// block per (chunk, t); all partial loads of a lane are in flight together.
 
-__global__ __launch_bounds__(kBlock) void k_ctg_finalize(EvalArgs a) {
-  __shared__ double sv[kBlock];
-  __shared__ int si[kBlock];
-  __shared__ double red[kBlock];
+__global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
-  const int t = blockIdx.x, tid = threadIdx.x;
+  const int t = blockIdx.y, kc = blockIdx.x, lane = threadIdx.x;
+  const int T = p.T, L = p.L, K = p.K, Kp = p.Kp;
+  const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
+  const double kt = p.dt[t] * p.c_s * beta;
+  const int k = kc * 64 + lane;
+  const size_t o = (size_t)t * Kp + k;
+  const size_t stride = (size_t)T * Kp;
+  const double zs = strided_sum<16>(w.zpart + o, a.nLb, stride);
+  const double ss = strided_sum<16>(w.spart + o, a.nLb, stride);
+  double z = -DBL_MAX, zsum = 0.0;
+  int idx = INT_MAX;
+  if (k < K) {
+    z = kt * ((double)(L - 1) * eps + zs);
+    w.zval[o] = z;
+    w.smean[o] = ss / (double)K;
+    idx = k;
+    zsum = z;
+  }
+  const double tot = wave_sum(zsum);
+  wave_argmax(z, idx);
+  if (lane == 0) {
+    const size_t c = (size_t)t * a.nKc + kc;
+    w.zmaxp[c] = z;
+    w.zargp[c] = (double)idx;
+    w.zsump[c] = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K5: per-(t, l) adjoint of the flows: dL/dF_tl (transposed, the A operand of
+// the adjoint product) and dL/dqmax2_tl, with weight 1/K for every
+// contingency plus 1 for the worst of the period (Table 1's two contingency
+// rows).  The worst contingency's own column is re-evaluated here; its
+// outage-correction term S* = sum_l LODF_lk* dP_tlk* belongs to dL/dF at the
+// outaged branch and is applied in k_final as a rank-1 term (per-chunk sums).
+
+__global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
+  __shared__ double red[16];
+  const DevProblem& p = a.p;
+  const DevWork& w = a.w;
+  const int t = blockIdx.y, lc = blockIdx.x, tid = threadIdx.x;
   const int T = p.T, L = p.L, K = p.K, Lp = p.Lp, Kp = p.Kp, Tp = p.Tp;
   const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
   const double kt = p.dt[t] * p.c_s * beta;
-  if (K == 0) {
-    for (int l = tid; l < Lp; l += kBlock) {
-      w.gfT[(size_t)l * Tp + t] = 0.0;
-      w.qtot[(size_t)t * Lp + l] = 0.0;
+  const int l = lc * kBlock + tid;
+  const bool hasl = l < L;
+  // independent loads first
+  double r = 0.0, q = 0.0, Fl = 0.0, q2l = 0.0, sm2 = 0.0, sm = 0.0;
+  int kk = -1;
+  if (hasl) {
+    const size_t o = (size_t)t * Lp + l;
+    if (K > 0) {  // without contingencies the partials were never written
+      r = strided_sum<16>(w.rpart + o, a.nKb, (size_t)T * Lp);
+      q = strided_sum<16>(w.qpart + o, a.nKb, (size_t)T * Lp);
     }
-    if (tid == 0) { w.tpart[a.toff.cmax + t] = 0.0; w.tpart[a.toff.cmean + t] = 0.0; }
-    return;
+    Fl = w.F[o];
+    q2l = w.q2[o];
+    sm2 = p.ctg_smax2[l];
+    sm = p.ctg_smax[l];
+    kk = p.kof[l];
   }
-  const double floor_ = (double)(L - 1) * eps;
-  const double invK = 1.0 / (double)K;
-  double best = -DBL_MAX;
-  int bi = INT_MAX;
-  double zs_local[1] = {0.0};
-  for (int k = tid; k < K; k += kBlock) {
-    double zs = 0.0, ss = 0.0;
-    for (int q = 0; q < a.nLb; ++q) {
-      const size_t o = ((size_t)q * T + t) * Kp + k;
-      zs += w.zpart[o];
-      ss += w.spart[o];
-    }
-    const double z = kt * (floor_ + zs);
-    w.zval[(size_t)t * Kp + k] = z;
-    w.smean[(size_t)t * Kp + k] = ss * invK;
-    if (z > best) { best = z; bi = k; }
-    zs_local[0] += z;
-  }
-  sv[tid] = best;
-  si[tid] = bi;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double v2 = sv[tid + s];
-      const int i2 = si[tid + s];
-      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
-    }
-    __syncthreads();
-  }
-  // a NaN penalty never wins a comparison; fall back to contingency 0 so that
-  // every index below stays in range
-  const int kstar = si[0] < K ? si[0] : 0;
-  const double zmax = sv[0];
-  block_sum<1>(zs_local, red);
-  if (tid == 0) {
-    w.tpart[a.toff.cmax + t] = zmax;
-    w.tpart[a.toff.cmean + t] = zs_local[0] * invK;
-  }
-  const double fks = w.Fk[(size_t)t * Kp + kstar];
-  const int bks = p.brk[kstar];
   double sacc[1] = {0.0};
-  for (int l = tid; l < Lp; l += kBlock) {
-    double r = 0.0, q = 0.0;
-    if (l < L) {
-      for (int kb = 0; kb < a.nKb; ++kb) {
-        const size_t o = ((size_t)kb * T + t) * Lp + l;
-        r += w.rpart[o];
-        q += w.qpart[o];
-      }
+  if (K > 0) {
+    // worst contingency of the period from the per-chunk partials (chunk order)
+    double zmax = w.zmaxp[(size_t)t * a.nKc];
+    int kstar = (int)w.zargp[(size_t)t * a.nKc];
+    double zsum = w.zsump[(size_t)t * a.nKc];
+    for (int c = 1; c < a.nKc; ++c) {
+      const size_t o = (size_t)t * a.nKc + c;
+      const double v = w.zmaxp[o];
+      const int i = (int)w.zargp[o];
+      if (better(v, i, zmax, kstar)) { zmax = v; kstar = i; }
+      zsum += w.zsump[o];
+    }
+    if (!(kstar >= 0 && kstar < K)) kstar = 0;  // NaN penalties: keep every index in range
+    const double invK = 1.0 / (double)K;
+    if (hasl) {
       r *= invK;
       q *= invK;
-      if (l != bks) {
+      if (l != p.brk[kstar]) {
         const double lo = p.lodf[(size_t)l * Kp + kstar];
-        const double P = fma(lo, fks, w.F[(size_t)t * Lp + l]);
-        const double s2 = fma(P, P, w.q2[(size_t)t * Lp + l]);
-        if (s2 > p.ctg_smax2[l]) {
-          const double s = sqrt(s2);
-          const double em = fmax(s - p.ctg_smax[l], 0.0);
-          const double sig = sqrt(em * em + eps * eps);
-          if (sig > 0.0) {
-            const double gs = kt * em / sig;
-            const double dP = gs * P / s;
-            r += dP;
-            q += 0.5 * gs / s;
-            sacc[0] += lo * dP;
-          }
+        const double P = fma(lo, w.Fk[(size_t)t * Kp + kstar], Fl);
+        const double s2 = fma(P, P, q2l);
+        if (s2 > sm2) {
+          double dP, dq;
+          ctg_overload(P, s2, sm, eps, eps * eps, kt, dP, dq);
+          r += dP;
+          q += dq;
+          sacc[0] = lo * dP;
         }
       }
-      const int kk = p.kof[l];
       if (kk >= 0) r += w.smean[(size_t)t * Kp + kk];
     }
-    w.gfT[(size_t)l * Tp + t] = r;
-    w.qtot[(size_t)t * Lp + l] = q;
+    if (lc == 0 && tid == 0) {
+      w.tpart[a.toff.cmax + t] = zmax;
+      w.tpart[a.toff.cmean + t] = zsum * invK;
+      w.kstar[t] = (double)kstar;
+    }
+  } else if (lc == 0 && tid == 0) {
+    w.tpart[a.toff.cmax + t] = 0.0;
+    w.tpart[a.toff.cmean + t] = 0.0;
+    w.kstar[t] = 0.0;
+  }
+  if (l < Lp) {
+    w.gfT[(size_t)l * Tp + t] = hasl ? r : 0.0;
+    w.qtot[(size_t)t * Lp + l] = hasl ? q : 0.0;
+    if (t == 0)
+      for (int cc = T; cc < Tp; ++cc) w.gfT[(size_t)l * Tp + cc] = 0.0;
   }
   block_sum<1>(sacc, red);
-  if (tid == 0) w.gfT[(size_t)bks * Tp + t] += sacc[0];
+  if (tid == 0) w.smaxp[(size_t)t * a.nLc + lc] = sacc[0];
 }
 
 // ---------------------------------------------------------------------------
-// K5: adjoint DC product + branch reverse
+// K6: adjoint DC product + branch reverse
 
 __device__ void branch_reverse(const EvalArgs& a, int blk) {
   const DevProblem& p = a.p;
@@ -747,25 +897,33 @@ __device__ void branch_reverse(const EvalArgs& a, int blk) {
   w.epGT[ep + p.slot_to[l]] = -gd;
 }
 
+// Blocks [0, nslab * nsplit): the DC part of dL/dp, one 16-generator slab and
+// one slice of the branch dimension each (partials summed in k_final).
 __global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
   __shared__ double smem[kSlabLds];
   const DevProblem& p = a.p;
-  const int nslab = p.Np / 16;
-  if ((int)blockIdx.x < nslab) {
-    const int n0 = blockIdx.x * 16;
-    double* gpb = a.w.gpb;
-    const int T = p.T, Np = p.Np;
+  const int nslab = p.G16 / 16;
+  if ((int)blockIdx.x < nslab * a.nsplit) {
+    const int slab = blockIdx.x % nslab, sp = blockIdx.x / nslab;
+    const int n0 = slab * 16;
+    const int steps = p.Lp / 4;
+    const int per = (steps + a.nsplit - 1) / a.nsplit;
+    const int k0 = min(steps, sp * per) * 4, k1 = min(steps, (sp + 1) * per) * 4;
+    const int T = p.T, Tp = p.Tp, G16 = p.G16;
+    double* out = a.w.gpdc + (size_t)sp * T * G16;
+    const double* gfT = a.w.gfT;
+    auto aload = [=](int k, int row) -> double { return gfT[(size_t)k * Tp + row]; };
     auto epi = [=](int row, int col, double v) {
-      if (row < T) gpb[(size_t)row * Np + col] = v;
+      if (row < T) out[(size_t)row * G16 + col] = v;
     };
-    mfma_slab_dispatch(p.Tp / 16, a.w.gfT, p.Tp, p.isf, Np, p.Lp, n0, smem, epi);
+    mfma_slab_dispatch(p.Tp / 16, aload, p.isf_ga, G16, k0, k1, n0, smem, epi);
     return;
   }
-  branch_reverse(a, blockIdx.x - nslab);
+  branch_reverse(a, blockIdx.x - nslab * a.nsplit);
 }
 
 // ---------------------------------------------------------------------------
-// K6: bus reduce, generator assembly, gradient or fused Adam, terms
+// K7: bus reduce, generator assembly, gradient or fused Adam, terms
 
 struct AdamCtx {
   double b1, b2, eps, bc1, bc2;
@@ -823,33 +981,35 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     return;
   }
   const int gb = blockIdx.x - a.nb_bus;
-  if (gb < T) {
-    const int t = gb;
-    double s[1] = {0.0};
-    for (int i = tid; i < N; i += kBlock) s[0] += w.gpb[(size_t)t * p.Np + i];
-    block_sum<1>(s, smem);
-    const double meanG = s[0] / (double)N;
+  if (gb < a.nb_gen) {
+    // dL/dp: device partials, balance multiplier, and the DC part: the MFMA
+    // split partials plus the worst contingency's rank-1 term
+    // S*_t (ISF[br(k*)][bus(j)] - rowsum/N).
+    const int idx = gb * kBlock + tid;
+    if (idx >= T * G) return;
+    const int t = idx / G, j = idx - t * G;
+    const double smax = strided_sum<16>(w.smaxp + (size_t)t * a.nLc, a.nLc, 1);
+    const int bks = p.brk[(int)w.kstar[t]];
+    double dc = smax * p.isf_ga[(size_t)bks * p.G16 + j];
+    dc += strided_sum<16>(w.gpdc + (size_t)t * p.G16 + j, a.nsplit, (size_t)T * p.G16);
     const size_t TG = (size_t)T * G;
     const size_t base = 2 * (size_t)T * N;
-    for (int j = tid; j < G; j += kBlock) {
-      const size_t e = (size_t)t * G + j;
-      const int bus = p.gen_bus[j];
-      const size_t tb = (size_t)t * N + bus;
-      const double gp = w.gdev[e] - w.lamp[tb] + (w.gpb[(size_t)t * p.Np + bus] - meanG);
-      const double gq = w.gdev[TG + e] - w.lamq[tb];
-      const double gr = w.gdev[2 * TG + e];
-      const double gu = w.gdev[3 * TG + e];
-      if (a.fuse_adam) {
-        adam_entry(xm, a.m, a.v, base + e, gp, alpha[QG_C_P], 0.0, p.pmax[j], ac);
-        adam_entry(xm, a.m, a.v, base + TG + e, gq, alpha[QG_C_Q], p.qmin[j], p.qmax[j], ac);
-        adam_entry(xm, a.m, a.v, base + 2 * TG + e, gr, alpha[QG_C_R], 0.0, p.rmax[j], ac);
-        adam_entry(xm, a.m, a.v, base + 3 * TG + e, gu, alpha[QG_C_U], 0.0, 1.0, ac);
-      } else if (a.grad) {
-        a.grad[base + e] = gp;
-        a.grad[base + TG + e] = gq;
-        a.grad[base + 2 * TG + e] = gr;
-        a.grad[base + 3 * TG + e] = gu;
-      }
+    const size_t e = (size_t)t * G + j;
+    const size_t tb = (size_t)t * N + p.gen_bus[j];
+    const double gp = w.gdev[e] - w.lamp[tb] + dc;
+    const double gq = w.gdev[TG + e] - w.lamq[tb];
+    const double gr = w.gdev[2 * TG + e] - w.drs[t];
+    const double gu = w.gdev[3 * TG + e];
+    if (a.fuse_adam) {
+      adam_entry(xm, a.m, a.v, base + e, gp, alpha[QG_C_P], 0.0, p.pmax[j], ac);
+      adam_entry(xm, a.m, a.v, base + TG + e, gq, alpha[QG_C_Q], p.qmin[j], p.qmax[j], ac);
+      adam_entry(xm, a.m, a.v, base + 2 * TG + e, gr, alpha[QG_C_R], 0.0, p.rmax[j], ac);
+      adam_entry(xm, a.m, a.v, base + 3 * TG + e, gu, alpha[QG_C_U], 0.0, 1.0, ac);
+    } else if (a.grad) {
+      a.grad[base + e] = gp;
+      a.grad[base + TG + e] = gq;
+      a.grad[base + 2 * TG + e] = gr;
+      a.grad[base + 3 * TG + e] = gu;
     }
     return;
   }
@@ -914,6 +1074,10 @@ __global__ void k_set_step(int64_t* step, int64_t value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) step[0] = value;
 }
 
+__global__ void k_clear_flag(int* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_finite(const double* x, size_t n, int* flag) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < n && !isfinite(x[e])) flag[0] = 1;
@@ -921,6 +1085,11 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const double* x, size_t
 
 // ---------------------------------------------------------------------------
 // launchers
+
+size_t ctg_dyn_lds(const Problem* pr) {
+  const int lspan = pr->tile.bl * pr->tile.wl;
+  return (size_t)pr->tile.tc * (2 * lspan + kCtgLanes) * sizeof(double);
+}
 
 int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* grad,
                 double* terms_out, const EvalMode& mode, int fuse_adam, double* m, double* v,
@@ -939,8 +1108,13 @@ int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* gr
   a.nb_br = pr->nb_br;
   a.nb_bus = pr->nb_bus;
   a.bus_chunks = pr->bus_chunks;
+  a.nb_gen = pr->nb_gen;
+  a.nsplit = pr->nsplit;
   a.nLb = pr->nLb;
   a.nKb = pr->nKb;
+  a.nKc = pr->nKc;
+  a.nLc = pr->nLc;
+  a.tc = pr->tile.tc;
   a.toff = pr->toff;
   auto rec = [&](int i) {
     if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[i]), s);
@@ -951,20 +1125,25 @@ int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* gr
   hipLaunchKernelGGL(k_balance_flow, dim3(pr->nb_bus + pr->Lp / 16), dim3(kBlock), 0, s, a);
   rec(2);
   if (pr->K > 0) {
-    const dim3 grid(pr->nLb, pr->nKb), block(64 * pr->tile.wl);
+    const int ntc = (pr->T + pr->tile.tc - 1) / pr->tile.tc;
+    const dim3 grid(pr->nLb, pr->nKb, ntc), block(64 * pr->tile.wl);
+    const size_t lds = ctg_dyn_lds(pr);
     switch (pr->tile.bl) {
-      case 8: hipLaunchKernelGGL(k_ctg_main<8>, grid, block, 0, s, a); break;
-      case 16: hipLaunchKernelGGL(k_ctg_main<16>, grid, block, 0, s, a); break;
-      default: hipLaunchKernelGGL(k_ctg_main<32>, grid, block, 0, s, a); break;
+      case 8: hipLaunchKernelGGL(k_ctg_main<8>, grid, block, lds, s, a); break;
+      case 16: hipLaunchKernelGGL(k_ctg_main<16>, grid, block, lds, s, a); break;
+      default: hipLaunchKernelGGL(k_ctg_main<32>, grid, block, lds, s, a); break;
     }
   }
   rec(3);
-  hipLaunchKernelGGL(k_ctg_finalize, dim3(pr->T), dim3(kBlock), 0, s, a);
+  if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(pr->nKc, pr->T), dim3(64), 0, s, a);
   rec(4);
-  hipLaunchKernelGGL(k_adjoint, dim3(pr->Np / 16 + pr->nb_br), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc, pr->T), dim3(kBlock), 0, s, a);
   rec(5);
-  hipLaunchKernelGGL(k_final, dim3(pr->nb_bus + pr->T + 1), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_adjoint, dim3(pr->G16 / 16 * pr->nsplit + pr->nb_br), dim3(kBlock), 0, s,
+                     a);
   rec(6);
+  hipLaunchKernelGGL(k_final, dim3(pr->nb_bus + pr->nb_gen + 1), dim3(kBlock), 0, s, a);
+  rec(7);
   return (int)hipGetLastError();
 }
 
@@ -988,8 +1167,9 @@ int launch_set_step(const Problem* pr, const DevWork& w, int64_t value, void* st
 
 int launch_check_finite(const Problem* pr, const double* x, int* flag, void* stream) {
   const int nb = (int)((pr->n_x + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_check_finite, dim3(nb), dim3(kBlock), 0,
-                     static_cast<hipStream_t>(stream), x, (size_t)pr->n_x, flag);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, flag);
+  hipLaunchKernelGGL(k_check_finite, dim3(nb), dim3(kBlock), 0, s, x, (size_t)pr->n_x, flag);
   return (int)hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ QG_NCLASS = 6
 QG_NKERNELS = 8
 QG_CTG_ALL_NONBRIDGE, QG_CTG_LIST = 0, 1
 QG_FLAG_CHECK_FINITE = 0x1
-KERNEL_NAMES = ("k_forward", "k_balance_flow", "k_ctg_main", "k_ctg_finalize",
+KERNEL_NAMES = ("k_forward", "k_balance_flow", "k_ctg_main", "k_ctg_zred", "k_ctg_asm",
                 "k_adjoint", "k_final")
 
 _pd = C.POINTER(C.c_double)
@@ -111,7 +111,7 @@ _sig = {
     "qg_layout_of": (C.c_int, [_vp, C.POINTER(qg_layout)]),
     "qg_ctg_list": (C.c_int, [_vp, _pi, C.c_int32]),
     "qg_problem_dims": (C.c_int, [_vp, _pi, C.c_int32]),
-    "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "qg_eval_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp, _vp]),
     "qg_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double * QG_NCLASS,
                                C.POINTER(qg_adam_cfg), _vp]),
@@ -221,15 +221,15 @@ def qg_ctg_list(h, k):
 
 
 def qg_problem_dims(h):
-    out = np.zeros(15, dtype=np.int32)
-    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 15), "qg_problem_dims")
-    keys = ("N", "L", "G", "T", "M", "K", "Lp", "Kp", "Np", "N4", "Tp", "nLb", "nKb",
-            "ctg_bl", "ctg_wl")
+    out = np.zeros(16, dtype=np.int32)
+    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 16), "qg_problem_dims")
+    keys = ("N", "L", "G", "T", "M", "K", "Lp", "Kp", "G16", "G4", "Tp", "nLb", "nKb",
+            "ctg_bl", "ctg_wl", "ctg_tc")
     return dict(zip(keys, (int(v) for v in out)))
 
 
-def qg_set_ctg_tile(h, bl, wl):
-    _check(lib.qg_set_ctg_tile(h, bl, wl), "qg_set_ctg_tile")
+def qg_set_ctg_tile(h, bl, wl, tc=0):
+    _check(lib.qg_set_ctg_tile(h, bl, wl, tc), "qg_set_ctg_tile")
 
 
 def qg_eval_grad(h, d_x, d_grad, d_terms, hom, d_ws, stream):
@@ -315,8 +315,8 @@ class Problem:
     def ctg_list(self):
         return qg_ctg_list(self.handle, self.K)
 
-    def set_ctg_tile(self, bl, wl):
-        qg_set_ctg_tile(self.handle, bl, wl)
+    def set_ctg_tile(self, bl, wl, tc=0):
+        qg_set_ctg_tile(self.handle, bl, wl, tc)
         self.dims = qg_problem_dims(self.handle)
 
     def new_vector(self, host=None):
@@ -366,5 +366,5 @@ def report_dict(rep):
                 time_to_gap_s=rep.time_to_gap_s, final_loss=rep.final_loss,
                 final_score=rep.final_score,
                 terms=dict(zip(TERM_NAMES, list(rep.terms))),
-                kernel_ms=dict(zip(KERNEL_NAMES, list(rep.kernel_ms)[:6])),
-                kernel_calls=dict(zip(KERNEL_NAMES, list(rep.kernel_calls)[:6])))
+                kernel_ms=dict(zip(KERNEL_NAMES, list(rep.kernel_ms)[:len(KERNEL_NAMES)])),
+                kernel_calls=dict(zip(KERNEL_NAMES, list(rep.kernel_calls)[:len(KERNEL_NAMES)])))

@@ -142,13 +142,14 @@ def test_bitwise_deterministic(qg):
     assert np.array_equal(t1, t2) and np.array_equal(g1, g2)
 
 
-@pytest.mark.parametrize("bl,wl", [(8, 2), (8, 4), (16, 1), (16, 4), (32, 2), (32, 8)])
-def test_ctg_tile_invariance(qg, bl, wl):
+@pytest.mark.parametrize("bl,wl,tc", [(8, 2, 0), (8, 4, 1), (8, 4, 7), (16, 1, 0),
+                                      (16, 4, 5), (32, 2, 0), (32, 8, 3), (8, 8, 8)])
+def test_ctg_tile_invariance(qg, bl, wl, tc):
     c = case("c2")
     prob = qg.Problem(c)
     x = synth.random_point(c, 10, spread=0.3)
     t0, g0 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
-    prob.set_ctg_tile(bl, wl)
+    prob.set_ctg_tile(bl, wl, tc)
     t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
     np.testing.assert_allclose(t1, t0, rtol=1e-12)
     assert_grad_close(c, g1, g0, tol=1e-12)
