@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ctg-tile", default="")
+    ap.add_argument("--eager", action="store_true",
+                    help="plain launches instead of graph replay (for counter runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, one device-to-device copy of this size "
+                         "(calibrates the byte counters of a profile)")
     return ap.parse_args()
 
 
@@ -50,17 +55,49 @@ def kernel_work(case, dims):
     T, N, L, G, K = case.n_period, case.n_bus, case.n_branch, case.n_gen, case.n_ctg
     D = 8
     return {
+        # per (t, l): x gathers and 15 doubles out; per (t, j): 4 in, 4 out;
+        # flow product 2 T G L flop (reported as bytes: the product is tiny)
+        "k_forward": ("hbm", D * (2 * T * N + 4 * T * G + T * L * 15 + T * G * 4 + T * L), "byte"),
         # every (t, l, k) element: post-outage flow and its square (2 FMA)
         "k_ctg_main": ("alu", 4.0 * T * L * K, "flop"),
-        # ISF product: 2 T N L flop
-        "k_balance_flow": ("mfma", 2.0 * T * (N - 1) * L, "flop"),
-        "k_adjoint": ("mfma", 2.0 * T * (N - 1) * L, "flop"),
-        # partial sums over l-blocks for every (t, k), over k-blocks for every (t, l)
+        # partial sums over l-blocks for every (t, k)
         "k_ctg_zred": ("hbm", D * T * K * (dims["nLb"] * 2 + 2), "byte"),
-        "k_ctg_asm": ("hbm", D * T * L * (dims["nKb"] * 2 + 6), "byte"),
-        "k_forward": ("hbm", D * (2 * T * N + 4 * T * G + T * L * 15), "byte"),
-        "k_final": ("hbm", D * (T * 2 * L * 2 + 3 * (2 * T * N + 4 * T * G)), "byte"),
+        # partial sums over k-blocks for every (t, l); balance over bus-sorted ends
+        "k_ctg_asm": ("hbm", D * (T * L * (dims["nKb"] * 2 + 6) + T * 2 * L * 2 + 4 * T * N), "byte"),
+        # adjoint product 2 T G L flop; branch reverse reads 9 coefficients, writes 4
+        "k_adjoint": ("hbm", D * (T * L * 13 + 2 * T * N + T * L), "byte"),
+        # endpoint adjoints, generator assembly and the fused Adam (48 B per entry)
+        "k_final": ("hbm", D * (T * 2 * L * 2 + 4 * T * G + 6 * (2 * T * N + 4 * T * G)), "byte"),
     }
+
+
+def kernel_source_digest():
+    """SHA-256 of the kernel source, to tell whether stored counters are current."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2310_06650_amd", "csrc", "qg_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic(kernel, config):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (profiles/<kernel>_<config>_traffic.md), or None when there is none or the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(case, seconds):
@@ -119,7 +156,7 @@ def main():
         v = prob.new_vector()
     stream.synchronize()
     common = dict(n_total=n_total, eps0=1e-1, epsf=1e-4, beta0=0.1, betaf=1.0, rho0=0.1,
-                  rhof=1.0, use_graph=1)
+                  rhof=1.0, use_graph=0 if args.eager else 1)
     alpha0, alphaf = [1e-3] * 6, [1e-5] * 6
     # warmup (also captures the graph)
     prob.solve(x, m, v, qg.solve_opts(args.warmup, alpha0, alphaf, iter0=0, **common))
@@ -152,7 +189,7 @@ def main():
         peak = PEAK_FP64_TFLOPS
         runit = "TFLOP/s"
     roof = dict(bound=bound, kernel=dom, achieved=achieved, peak=peak, unit=runit,
-                frac=achieved / peak, traffic=None,
+                frac=achieved / peak, traffic=stored_traffic(dom, args.config),
                 per_launch=f"{amount:.4g} {unit} algorithmic, mean {kms[dom] * 1e3:.2f} us/launch")
     out = dict(metric=METRIC, value=steps_per_s, unit="steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=1e3 * el / args.steps, higher_is_better=True,
@@ -166,6 +203,13 @@ def main():
                            parallelism="single GPU"),
                kernel_us={k: round(v * 1e3, 3) for k, v in kms.items()},
                final_score=rep.final_score, roofline=roof)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = n * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

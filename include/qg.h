@@ -76,6 +76,16 @@ enum { QG_CTG_ALL_NONBRIDGE = 0, QG_CTG_LIST = 1 };
 
 /* Flags for qg_build_opts.flags */
 #define QG_FLAG_CHECK_FINITE 0x1u /* qg_eval_grad rejects non-finite x (syncs) */
+/* Precision of the contingency map-reduce (eqs. (rank_correct), (sfr_pen)-(zctg)
+ * and their reverse).  Default: FP64 throughout.  With one of these flags the
+ * outage factors are stored in FP32 or in BF16 (rounded to nearest even), and
+ * the post-outage flows, penalties, derivatives and their sums over branches
+ * and contingencies are computed in FP32; their partial sums are handed to
+ * the FP64 remainder of the step.  The base-case flows, the sensitivity
+ * products, every other term and the Adam moments stay FP64.  At most one of
+ * the two may be set (ARG otherwise). */
+#define QG_FLAG_CTG_FP32 0x2u
+#define QG_FLAG_CTG_BF16 0x4u
 
 /* Grid description: host arrays, all FP64 per unit (100 MVA base) unless
  * stated; prices in $ per pu-hour, durations in hours. */
@@ -161,7 +171,9 @@ typedef struct {
   double final_loss;         /* objective at the last schedule point */
   double final_score;        /* -L at eps = 0, beta = 1, rho_scale = rhof */
   double terms[QG_NTERMS];   /* score-point terms at the end */
-  double kernel_ms[QG_NKERNELS]; /* mean duration per launch when profile = 1 */
+  /* mean duration per launch when profile = 1, in stream order: k_forward,
+   * k_ctg_main, k_ctg_zred, k_ctg_asm, k_adjoint, k_final (slots 6, 7 unused) */
+  double kernel_ms[QG_NKERNELS];
   int64_t kernel_calls[QG_NKERNELS];
 } qg_solve_report;
 
@@ -242,16 +254,19 @@ qg_status qg_solve(qg_problem* prob, double* d_x, double* d_m, double* d_v,
  * N, L, G, T, M, K, Lp, Kp, G16, G4, Tp, nLb, nKb, ctg_bl, ctg_wl, ctg_tc
  * (Lp = L rounded up to 64, Kp = K up to 64, G16 = G up to 16, G4 = G up to 4,
  * Tp = T up to 16; nLb, nKb = partial-sum counts of the contingency
- * map-reduce; ctg_bl, ctg_wl, ctg_tc = its tile).  capacity must be >= 16.
+ * map-reduce; ctg_bl, ctg_wl, ctg_tc = its tile).  With capacity >= 17,
+ * dims[16] = storage of the outage factors (0 FP64, 1 FP32, 2 BF16).
+ * capacity must be >= 16.
  */
 qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacity);
 
 /*
  * Tile of the contingency map-reduce: bl branches per wavefront (8, 16 or 32),
  * wl wavefronts per block (1, 2, 4 or 8) with bl*wl >= 16, and tc periods per
- * block (0: a default from the problem size; at most 8 and at most what the
- * LDS staging budget allows).  The results do not depend on the tile except through the order
- * of floating-point sums.  Used by the autotuner.  Errors: ARG.
+ * block (0: a default from the problem size; at most 8, and at most T).  The
+ * results do not depend on the tile except through the order of
+ * floating-point sums.  A step graph cached by qg_solve is re-captured after
+ * a change.  Errors: ARG.
  */
 qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
 

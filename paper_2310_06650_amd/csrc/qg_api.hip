@@ -124,9 +124,10 @@ qg_status qg_problem_dims(const qg_problem* pr, int32_t* d, int32_t capacity) {
   if (s != QG_OK) return s;
   if (!d || capacity < 16) return fail(QG_ERR_ARG, "dims needs 16 entries");
   const qg::Problem& p = pr->p;
-  const int32_t v[16] = {p.N, p.L, p.G, p.T, p.M, p.K, p.Lp, p.Kp, p.G16, p.G4, p.Tp,
-                         p.nLb, p.nKb, p.tile.bl, p.tile.wl, p.tile.tc};
-  std::memcpy(d, v, sizeof(v));
+  const int32_t v[17] = {p.N,  p.L,   p.G,   p.T,       p.M,       p.K,       p.Lp,
+                         p.Kp, p.G16, p.G4,  p.Tp,      p.nLb,     p.nKb,     p.tile.bl,
+                         p.tile.wl,   p.tile.tc, p.dp.lodf_kind};
+  std::memcpy(d, v, sizeof(int32_t) * (capacity >= 17 ? 17 : 16));
   return QG_OK;
 }
 
@@ -141,8 +142,6 @@ qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl, int32_t tc) {
   if (tc <= 0) tc = qg::default_ctg_tc(p.T, span);
   if (tc > p.T) tc = p.T;
   if (tc > qg::kCtgMaxTc) return fail(QG_ERR_ARG, "at most 8 periods per block");
-  if (tc * (2 * span + qg::kCtgLanes) > qg::kCtgStageDoubles)
-    return fail(QG_ERR_ARG, "period chunk too large for the LDS staging budget");
   p.tile = qg::CtgTile{bl, wl, tc};
   p.nLb = (p.Lp + span - 1) / span;
   return QG_OK;
@@ -286,7 +285,7 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   const bool profile = o->profile != 0;
   const bool graph = o->use_graph != 0 && !profile;
   hipEvent_t evs[QG_NKERNELS];
-  constexpr int kKernels = 7;
+  constexpr int kKernels = 6;
   if (profile)
     for (int i = 0; i <= kKernels; ++i) HIP_TRY(hipEventCreate(&evs[i]), "event");
 
@@ -302,6 +301,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     // the schedule constants are kernel arguments, so a different schedule
     // needs a new capture as well
     if (hit && std::memcmp(&pr->p.graph_mode, &sm, sizeof(sm)) != 0) hit = false;
+    // and so is the contingency tile (grid and LDS size of the map-reduce)
+    const qg::CtgTile& gt = pr->p.graph_tile;
+    if (hit && (gt.bl != p.tile.bl || gt.wl != p.tile.wl || gt.tc != p.tile.tc)) hit = false;
     if (!hit) {
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; pr->p.graph_exec = nullptr; }
       hipGraph_t g;
@@ -316,6 +318,7 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
       std::memcpy(pr->p.graph_key, key, sizeof(key));
       pr->p.graph_steps = gsteps;
       std::memcpy(&pr->p.graph_mode, &sm, sizeof(sm));
+      pr->p.graph_tile = p.tile;
     }
   }
 

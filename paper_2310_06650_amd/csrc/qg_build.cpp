@@ -93,6 +93,15 @@ bool find_bridges(int N, int L, const int32_t* fr, const int32_t* to,
 // qg_problem_sizes) and the offsets (for the image).
 constexpr int kNConst = 46;
 
+// FP32 -> BF16 with round to nearest even; NaN stays a (quiet) NaN.
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+  const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+
 struct ConstLayout {
   size_t off[kNConst];
   size_t total;
@@ -116,7 +125,7 @@ ConstLayout const_layout(const Problem& p) {
       T * D, T * D, T * D,                        // dt, rsv_req, sum_load
       (size_t)p.G4 * p.Lp * D,                    // isf_gT
       (size_t)p.Lp * p.G16 * D,                   // isf_ga
-      (size_t)p.Lp * p.Kp * D,                    // lodf
+      (size_t)p.Lp * p.Kp * lodf_elem_bytes(lodf_kind_of(p.flags)),  // lodf (FP64/FP32/BF16)
       T * (size_t)p.Lp * D,                       // cload
       (size_t)p.Lp * D};                          // rsum
   ConstLayout c;
@@ -180,9 +189,9 @@ WorkLayout work_layout(const Problem& p) {
 
 int default_ctg_tc(int T, int lspan) {
   // periods per block of the contingency map-reduce: enough blocks to give
-  // the chip several wavefronts per SIMD, within the LDS staging budget
-  const int cap = std::max(1, kCtgStageDoubles / (2 * lspan + kCtgLanes));
-  int tc = std::min(std::min(T, cap), kCtgMaxTc);
+  // the chip several wavefronts per SIMD
+  (void)lspan;
+  int tc = std::min(T, kCtgMaxTc);
   if (T > 8) tc = std::min(tc, (T + 2) / 3);
   return std::max(1, tc);
 }
@@ -269,6 +278,10 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   p->G4 = (int)round_up(G, 4);
   p->Tp = (int)round_up(T, 16);
   p->n_x = 2LL * T * N + 4LL * T * G;
+  if ((o->flags & QG_FLAG_CTG_FP32) && (o->flags & QG_FLAG_CTG_BF16))
+    return fail(QG_ERR_ARG, "at most one contingency precision flag");
+  if (o->flags & ~(uint32_t)(QG_FLAG_CHECK_FINITE | QG_FLAG_CTG_FP32 | QG_FLAG_CTG_BF16))
+    return fail(QG_ERR_ARG, "unknown build flag");
   p->flags = o->flags;
   p->nb_br = (int)((int64_t(T) * L + kBlock - 1) / kBlock);
   p->bus_chunks = (N + kBlock - 1) / kBlock;
@@ -542,7 +555,15 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
 
   // ---- outage factors, NaN on the outaged branch itself and on padding
   {
-    double* lo = reinterpret_cast<double*>(img.data() + cl.off[43]);
+    const int kind = lodf_kind_of(p->flags);
+    std::vector<double> lo_buf;
+    double* lo;
+    if (kind == kLodfF64) {
+      lo = reinterpret_cast<double*>(img.data() + cl.off[43]);
+    } else {
+      lo_buf.resize((size_t)Lp * Kp);
+      lo = lo_buf.data();
+    }
     const double qnan = std::numeric_limits<double>::quiet_NaN();
     std::fill(lo, lo + (size_t)Lp * Kp, qnan);
     std::vector<double> denom(K);
@@ -563,6 +584,13 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
         out[k] = (row[d->br_from[bk]] - row[d->br_to[bk]]) / denom[k];
       }
     });
+    if (kind == kLodfF32) {
+      float* o32 = reinterpret_cast<float*>(img.data() + cl.off[43]);
+      for (size_t e = 0; e < (size_t)Lp * Kp; ++e) o32[e] = (float)lo[e];
+    } else if (kind == kLodfBF16) {
+      uint16_t* o16 = reinterpret_cast<uint16_t*>(img.data() + cl.off[43]);
+      for (size_t e = 0; e < (size_t)Lp * Kp; ++e) o16[e] = to_bf16((float)lo[e]);
+    }
   }
 
   // ---- scalars
@@ -590,7 +618,12 @@ void rebase_pointers(Problem* p, void* arena) {
   dp.u0 = D(28); dp.con = D(29); dp.csu = D(30); dp.csd = D(31); dp.cr = D(32);
   dp.seg_cost = D(33); dp.seg_size = D(34); dp.pcum = D(35);
   dp.load_p = D(36); dp.load_q = D(37); dp.dt = D(38); dp.rsv_req = D(39);
-  dp.sum_load = D(40); dp.isf_gT = D(41); dp.isf_ga = D(42); dp.lodf = D(43);
+  dp.sum_load = D(40); dp.isf_gT = D(41); dp.isf_ga = D(42);
+  dp.lodf_kind = lodf_kind_of(p->flags);
+  dp.lodf = dp.lodf_kind == kLodfF64 ? D(43) : nullptr;
+  dp.lodf32 = dp.lodf_kind == kLodfF32 ? reinterpret_cast<const float*>(base + cl.off[43]) : nullptr;
+  dp.lodf16 =
+      dp.lodf_kind == kLodfBF16 ? reinterpret_cast<const uint16_t*>(base + cl.off[43]) : nullptr;
   dp.cload = D(44); dp.rsum = D(45);
   p->arena = arena;
 }

@@ -15,13 +15,19 @@ constexpr int kMaxT = 64;          // periods per problem (4 MFMA row tiles of 1
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kCtgLanes = 64;      // contingencies per wavefront in the map-reduce
 constexpr int kParams = 16;        // doubles in the per-step parameter block
-constexpr int kCtgStageDoubles = 5120;  // LDS staging budget of the contingency kernel
 constexpr int kCtgMaxTc = 8;            // periods per block of the contingency kernel
 constexpr int kAdjStepsPerBlock = 64;   // MFMA k-steps per block of the adjoint product
 constexpr int kSchedCap = 2048;         // solve steps per uploaded schedule table
 constexpr int kSchedStride = 16;        // doubles per step in the schedule table
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Storage kind of the outage factors, from the build flags.
+enum LodfKind { kLodfF64 = 0, kLodfF32 = 1, kLodfBF16 = 2 };
+inline int lodf_kind_of(uint32_t flags) {
+  return (flags & QG_FLAG_CTG_BF16) ? kLodfBF16 : (flags & QG_FLAG_CTG_FP32) ? kLodfF32 : kLodfF64;
+}
+inline size_t lodf_elem_bytes(int kind) { return kind == kLodfF64 ? 8 : kind == kLodfF32 ? 4 : 2; }
 
 // Device view of the constant arena (all pointers into caller memory).
 struct DevProblem {
@@ -58,6 +64,9 @@ struct DevProblem {
   const double* cload;   // [T][Lp]   sum_i ISF[l][i] load_p[t][i]
   const double* rsum;    // [Lp]      sum_i ISF[l][i]
   const double* lodf;    // [Lp][Kp]  outage factors; NaN marks (k,k) and padding
+  const float* lodf32;   //           the same in FP32 (QG_FLAG_CTG_FP32)
+  const uint16_t* lodf16;  //         the same in BF16 (QG_FLAG_CTG_BF16)
+  int lodf_kind;         // 0 FP64, 1 FP32, 2 BF16 (one of the three pointers is set)
   // prices
   double c_p, c_q, c_s, c_ang, ang_max, c_rsv, rho, vload;
 };
@@ -143,6 +152,7 @@ struct Problem {
   const void* graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int graph_steps = 0;
   EvalMode graph_mode{};
+  CtgTile graph_tile{};   // contingency tile the cached graph was captured with
 };
 
 // Host build products (before upload).

@@ -3,15 +3,15 @@
 // Stage map (one launch each, in stream order):
 //   k_forward       per-(t, branch) AC flows and penalties          (Section II-B Ex. 1, 4; II-G)
 //                   + one block per period: device terms, reserve     (Ex. 2, 3; eq. (nlp_updated))
-//                     shortfall and the period's total output
-//   k_balance_flow  per-(t, bus) power balance from bus-sorted endpoint flows
-//                     (LDS-staged segmented sums)                      (Ex. 4)
+//                     shortfall
 //                   + base-case DC flows on FP64 MFMA:                 (eqs. (Yb_solve)-(p_flow))
 //                     F_t = ISF[:, gen] p_t - ISF load_t - mean_t ISF 1 (uniform slack)
 //   k_ctg_main      per-(t, l, k) outage flows F_l + LODF_lk F_k, their (eqs. (rank_correct),
 //                     penalties and partial reductions                   (sfr_pen)-(zctg), (2nd_lin_sys))
 //   k_ctg_zred      per-(t, k) penalties z_tk, per-chunk worst and sum
 //   k_ctg_asm       per-(t, l) dL/dF and dL/dqmax2 (mean + worst-contingency weights)
+//                   + per-(t, bus) power balance from bus-sorted endpoint flows
+//                     (LDS-staged segmented sums)                      (Ex. 4)
 //   k_adjoint       dL/dp_tj (DC part) = sum_l dL/dF_tl (ISF[l][bus(j)] - rowsum_l/N)
 //                     on FP64 MFMA, split over the branch dimension      (eqs. (2nd_lin_sys), (correction))
 //                   + per-(t, branch) reverse of the AC flows into bus-sorted endpoint slots
@@ -25,6 +25,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 #include "qg_internal.h"
 
@@ -112,6 +113,111 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_f64<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
   v += dpp_f64<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
   return readlane_f64(v, 63);
+}
+
+// Cross-half exchanges of gfx950: permlane32_swap trades lanes 32..63 of
+// its first operand with lanes 0..31 of its second, permlane16_swap the odd
+// 16-lane rows of the first with the even rows of the second.  After either,
+// the sum of the two results holds, in the lanes whose exchanged bit is 0,
+// a summed over the lane pair, and in the others b summed over the pair.
+template <int W>
+__device__ __forceinline__ double swap_add(double a, double b) {
+  const unsigned alo = __double2loint(a), ahi = __double2hiint(a);
+  const unsigned blo = __double2loint(b), bhi = __double2hiint(b);
+  unsigned xlo, ylo, xhi, yhi;
+  if constexpr (W == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    xlo = l[0]; ylo = l[1]; xhi = h[0]; yhi = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    xlo = l[0]; ylo = l[1]; xhi = h[0]; yhi = h[1];
+  }
+  return __hiloint2double((int)xhi, (int)xlo) + __hiloint2double((int)yhi, (int)ylo);
+}
+
+// Wavefront totals of two per-lane values at once (all lanes active): lanes
+// 0..31 return the sum of a over the 64 lanes, lanes 32..63 the sum of b.
+// The 32-lane swap leaves a's pair sums in the low half and b's in the high
+// half, the 16-lane swap adds the two rows of each half, and four DPP steps
+// finish inside each row.
+__device__ __forceinline__ double pair_sum(double a, double b) {
+  double v = swap_add<32>(a, b);
+  v = swap_add<16>(v, v);
+  v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);   // row_mirror
+  return v;
+}
+
+// Read-only view of device memory in the constant address space: loads at
+// wavefront-uniform addresses through it become scalar loads into SGPRs.
+// Only for data that no kernel of the same launch writes.
+typedef __attribute__((address_space(4))) const double cdouble;
+__device__ __forceinline__ const cdouble* as_const(const double* q) {
+  return (const cdouble*)q;
+}
+
+// a * b + c with c wavefront-uniform, read straight from its SGPR pair (one
+// VOP3 instruction instead of a copy into VGPRs and an accumulate).
+__device__ __forceinline__ double fma_uniform_c(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+}
+__device__ __forceinline__ float fma_uniform_c(float a, float b, float c) {
+  float d;
+  asm("v_fma_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+}
+
+// ---- FP32 counterparts for the reduced-precision contingency map-reduce
+
+// 1/sqrt(x) for x > 0 in FP32: the hardware estimate and one Newton step.
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  const float r = fmaf(-x * y, y, 1.0f);
+  return fmaf(0.5f * y, r, y);
+}
+
+__device__ __forceinline__ float readlane_any(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double readlane_any(double v, int lane) { return readlane_f64(v, lane); }
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// FP32 form of pair_sum (the same lane pattern, one register per value).
+__device__ __forceinline__ float pair_sum(float a, float b) {
+  const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  float v = __uint_as_float(x[0]) + __uint_as_float(x[1]);
+  const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  v = __uint_as_float(y[0]) + __uint_as_float(y[1]);
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  v += dpp_f32<0x141>(v);
+  v += dpp_f32<0x140>(v);
+  return v;
+}
+
+// Outage factor of the stored kind, widened to the arithmetic type.
+__device__ __forceinline__ double lodf_load(const double* q, size_t e) { return q[e]; }
+__device__ __forceinline__ float lodf_load(const float* q, size_t e) { return q[e]; }
+__device__ __forceinline__ float lodf_load(const uint16_t* q, size_t e) {
+  return __uint_as_float((unsigned)q[e] << 16);
+}
+__device__ __forceinline__ double lodf_value(const DevProblem& p, int l, int k) {
+  const size_t e = (size_t)l * p.Kp + k;
+  if (p.lodf_kind == kLodfF64) return p.lodf[e];
+  if (p.lodf_kind == kLodfF32) return (double)p.lodf32[e];
+  return (double)lodf_load(p.lodf16, e);
 }
 
 // Largest value over the 64 lanes of a wavefront, ties to the smaller index
@@ -222,20 +328,20 @@ __device__ void resolve_params(const EvalArgs& a, StepParams& sp) {
 // Contribution of one overloaded outage element: with s = sqrt(s2),
 // e = s - s_ctg and sigma = sqrt(max(e,0)^2 + eps^2), returns sigma - eps (the
 // penalty above its floor), and dC/dP, dC/dqmax2 scaled by kt.
-__device__ __forceinline__ double ctg_overload(double P, double s2, double smx, double eps,
-                                               double eps2, double kt, double& dP, double& dq) {
-  const double rs = rsqrt_nr(s2);
-  const double s = s2 * rs;
-  const double em = fmax(s - smx, 0.0);
-  const double w2 = fma(em, em, eps2);
-  dP = 0.0;
-  dq = 0.0;
-  if (!(w2 > 0.0)) return 0.0;
-  const double rw = rsqrt_nr(w2);
-  const double sig = w2 * rw;
-  const double gs = kt * em * rw;
+template <typename R>
+__device__ __forceinline__ R ctg_overload(R P, R s2, R smx, R eps, R eps2, R kt, R& dP, R& dq) {
+  const R rs = rsqrt_nr(s2);
+  const R s = s2 * rs;
+  const R em = fmax(s - smx, R(0));
+  const R w2 = fma(em, em, eps2);
+  // w2 = 0 only when eps = 0 and s sits exactly on the rating: sigma = 0
+  // there and the one-sided derivative is taken as 0
+  const bool pos = w2 > R(0);
+  const R rw = rsqrt_nr(pos ? w2 : R(1));
+  const R sig = w2 * rw;
+  const R gs = pos ? kt * em * rw : R(0);
   dP = gs * P * rs;
-  dq = 0.5 * gs * rs;
+  dq = R(0.5) * gs * rs;
   return sig - eps;
 }
 
@@ -422,8 +528,8 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
 // 2-3), the penalised device constraints of eq. (nlp_updated) and their
 // partials.  The next period's terms that depend on this period's p and u
 // are included, so each thread writes only its own partials.  The block also
-// sums the period's output (for the uniform slack of the DC flows) and
-// reserve (for the shortfall penalty), and zeroes the padding read later.
+// sums the period's reserve (for the shortfall penalty) and zeroes the
+// padding read later.
 __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, double* lds) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
@@ -437,7 +543,7 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
   const double dtt = p.dt[t];
   const double kpen = sp.rho_s * p.rho * sp.beta * dtt;
   const double eps = sp.eps;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dev, pen, sum p, sum r
+  double acc[3] = {0.0, 0.0, 0.0};  // dev, pen, sum r
   for (int j = tid; j < G; j += kBlock) {
     const size_t e = (size_t)t * G + j;
     const double pj = xP[e], qj = xQ[e], rj = xR[e], uj = xU[e];
@@ -500,25 +606,74 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
     w.gdev[3 * TG + e] = gu;
     acc[0] += dev;
     acc[1] += kpen * pen;
-    acc[2] += pj;
-    acc[3] += rj;
+    acc[2] += rj;
   }
-  block_sum<4>(acc, lds);
-  const double short_ = p.rsv_req[t] - acc[3];
+  block_sum<3>(acc, lds);
+  const double short_ = p.rsv_req[t] - acc[2];
   const double krs = dtt * p.c_rsv * sp.beta;
   if (tid == 0) {
     w.tpart[a.toff.dev + t] = acc[0];
     w.tpart[a.toff.pen + t] = acc[1];
     w.tpart[a.toff.rsv + t] = krs * soft_relu(short_, eps);
     w.drs[t] = krs * soft_relu_d(short_, eps);
-    w.psum[t] = acc[2];
   }
   for (int l = p.L + tid; l < p.Lp; l += kBlock) w.q2[(size_t)t * p.Lp + l] = 0.0;
   for (int k = p.K + tid; k < p.Kp; k += kBlock) w.Fk[(size_t)t * p.Kp + k] = 0.0;
 }
 
+// LDS of a kernel that runs both segmented sums and an MFMA slab: the slab
+// keeps four wavefronts x up to 4 row tiles x 256 partial results.
+constexpr int kSlabLds = 4 * 4 * 256;
+static_assert(kSlabLds >= 2 * kSegChunk + 8 * kBlock, "LDS carve");
+
+// Base-case DC flows of 16 branches for every period, on FP64 MFMA:
+// F[t][l] = sum_j p_tj ISF[l][bus(j)] - ISF load_t - mean_t rowsum_l, with
+// mean_t = (sum_j p_tj - sum_i load_ti) / N the uniform slack; also the
+// outaged branches' flows.  The block first sums each period's output itself
+// (a fixed order, so every slab sees the same mean).
+__device__ void flow_slab(const EvalArgs& a, int slab, double* smem) {
+  const DevProblem& p = a.p;
+  const DevWork& w = a.w;
+  const int T = p.T, G = p.G, Lp = p.Lp, Kp = p.Kp, N = p.N;
+  const double* xP = a.x + 2 * (size_t)T * N;
+  double* ps = smem + kSlabLds;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = wv; t < T; t += kBlock / 64) {
+    double sum = 0.0;
+    for (int j = lane; j < G; j += 64) sum += xP[(size_t)t * G + j];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+      ps[t] = sum;
+      if (slab == 0) w.psum[t] = sum;
+    }
+  }
+  __syncthreads();
+  const int n0 = slab * 16;
+  double* F = w.F;
+  double* Fk = w.Fk;
+  const int* kof = p.kof;
+  const double* cload = p.cload;
+  const double* rsum = p.rsum;
+  const double* sum_load = p.sum_load;
+  auto aload = [=](int k, int row) -> double {
+    return (row < T && k < G) ? xP[(size_t)row * G + k] : 0.0;
+  };
+  auto epi = [=](int row, int col, double v) {
+    if (row < T) {
+      const double mean = (ps[row] - sum_load[row]) / (double)N;
+      const double f = (v - cload[(size_t)row * Lp + col]) - mean * rsum[col];
+      F[(size_t)row * Lp + col] = f;
+      const int k = kof[col];
+      if (k >= 0) Fk[(size_t)row * Kp + k] = f;
+    }
+  };
+  mfma_slab_dispatch(p.Tp / 16, aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
+}
+
+// Blocks [0, nb_br): branch forward; [nb_br, nb_br + T): one period each;
+// then Lp / 16 flow slabs.
 __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
-  __shared__ double lds[4 * kBlock];
+  __shared__ double smem[kSlabLds + kMaxT];
   StepParams sp;
   resolve_params(a, sp);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -530,84 +685,51 @@ __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
     pb[PB_BC1] = sp.bc1;
     pb[PB_BC2] = sp.bc2;
   }
-  if ((int)blockIdx.x < a.nb_br)
-    branch_forward(a, sp, blockIdx.x, lds);
+  const int b = blockIdx.x;
+  if (b < a.nb_br)
+    branch_forward(a, sp, b, smem);
+  else if (b < a.nb_br + a.p.T)
+    period_block(a, sp, b - a.nb_br, smem);
   else
-    period_block(a, sp, blockIdx.x - a.nb_br, lds);
+    flow_slab(a, b - a.nb_br - a.p.T, smem);
 }
 
-// ---------------------------------------------------------------------------
-// K2: bus balance + base-case DC flows
-
-// LDS of a kernel that runs both segmented sums and an MFMA slab: the slab
-// keeps four wavefronts x up to 4 row tiles x 256 partial results.
-constexpr int kSlabLds = 4 * 4 * 256;
-static_assert(kSlabLds >= 2 * kSegChunk + 8 * kBlock, "LDS carve");
-
-__global__ __launch_bounds__(kBlock) void k_balance_flow(EvalArgs a) {
-  __shared__ double smem[kSlabLds];
+// Per-(t, bus) power balance (Example 4): segmented sums of the bus's
+// endpoint flows staged through LDS, minus its generators; multipliers and
+// the soft-abs value.
+__device__ void bus_balance(const EvalArgs& a, int blk, double* smem) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int tid = threadIdx.x;
-  if ((int)blockIdx.x < a.nb_bus) {
-    const int t = blockIdx.x / a.bus_chunks;
-    const int c = blockIdx.x - t * a.bus_chunks;
-    const int i0 = c * kBlock;
-    const int nbus = min(kBlock, p.N - i0);
-    const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
-    const double* src[2] = {w.epP + (size_t)t * p.twoL, w.epQ + (size_t)t * p.twoL};
-    double fl[2];
-    bus_segsum<2>(src, p.bptr, i0, nbus, smem, fl);
-    double part[1] = {0.0};
-    if (tid < nbus) {
-      const int i = i0 + tid;
-      const double* xP = a.x + 2 * (size_t)p.T * p.N;
-      const double* xQ = xP + (size_t)p.T * p.G;
-      double sp_ = 0.0, sq = 0.0;
-      for (int g = p.gptr[i]; g < p.gptr[i + 1]; ++g) {
-        const size_t e = (size_t)t * p.G + p.glist[g];
-        sp_ += xP[e];
-        sq += xQ[e];
-      }
-      const size_t ti = (size_t)t * p.N + i;
-      const double dp = p.load_p[ti] + fl[0] - sp_;
-      const double dq = p.load_q[ti] + fl[1] - sq;
-      const double kb = p.dt[t] * beta;
-      w.lamp[ti] = kb * p.c_p * soft_abs_d(dp, eps);
-      w.lamq[ti] = kb * p.c_q * soft_abs_d(dq, eps);
-      part[0] = kb * (p.c_p * sqrt(dp * dp + eps * eps) + p.c_q * sqrt(dq * dq + eps * eps));
+  const int t = blk / a.bus_chunks;
+  const int c = blk - t * a.bus_chunks;
+  const int i0 = c * kBlock;
+  const int nbus = min(kBlock, p.N - i0);
+  const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
+  const double* src[2] = {w.epP + (size_t)t * p.twoL, w.epQ + (size_t)t * p.twoL};
+  double fl[2];
+  bus_segsum<2>(src, p.bptr, i0, nbus, smem, fl);
+  double part[1] = {0.0};
+  if (tid < nbus) {
+    const int i = i0 + tid;
+    const double* xP = a.x + 2 * (size_t)p.T * p.N;
+    const double* xQ = xP + (size_t)p.T * p.G;
+    double sp_ = 0.0, sq = 0.0;
+    for (int g = p.gptr[i]; g < p.gptr[i + 1]; ++g) {
+      const size_t e = (size_t)t * p.G + p.glist[g];
+      sp_ += xP[e];
+      sq += xQ[e];
     }
-    block_sum<1>(part, smem);
-    if (tid == 0) w.tpart[a.toff.bal + blockIdx.x] = part[0];
-    return;
+    const size_t ti = (size_t)t * p.N + i;
+    const double dp = p.load_p[ti] + fl[0] - sp_;
+    const double dq = p.load_q[ti] + fl[1] - sq;
+    const double kb = p.dt[t] * beta;
+    w.lamp[ti] = kb * p.c_p * soft_abs_d(dp, eps);
+    w.lamq[ti] = kb * p.c_q * soft_abs_d(dq, eps);
+    part[0] = kb * (p.c_p * sqrt(dp * dp + eps * eps) + p.c_q * sqrt(dq * dq + eps * eps));
   }
-  // F[t][l] = sum_j p_tj ISF[l][bus(j)] - ISF load_t - mean_t rowsum_l, with
-  // mean_t = (sum_j p_tj - sum_i load_ti) / N the uniform slack; also the
-  // outaged branches' flows
-  const int slab = blockIdx.x - a.nb_bus;
-  const int n0 = slab * 16;
-  double* F = w.F;
-  double* Fk = w.Fk;
-  const int T = p.T, G = p.G, Lp = p.Lp, Kp = p.Kp, N = p.N;
-  const int* kof = p.kof;
-  const double* xP = a.x + 2 * (size_t)T * N;
-  const double* cload = p.cload;
-  const double* rsum = p.rsum;
-  const double* psum = w.psum;
-  const double* sum_load = p.sum_load;
-  auto aload = [=](int k, int row) -> double {
-    return (row < T && k < G) ? xP[(size_t)row * G + k] : 0.0;
-  };
-  auto epi = [=](int row, int col, double v) {
-    if (row < T) {
-      const double mean = (psum[row] - sum_load[row]) / (double)N;
-      const double f = (v - cload[(size_t)row * Lp + col]) - mean * rsum[col];
-      F[(size_t)row * Lp + col] = f;
-      const int k = kof[col];
-      if (k >= 0) Fk[(size_t)row * Kp + k] = f;
-    }
-  };
-  mfma_slab_dispatch(p.Tp / 16, aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
+  block_sum<1>(part, smem);
+  if (tid == 0) w.tpart[a.toff.bal + blk] = part[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -616,19 +738,25 @@ __global__ __launch_bounds__(kBlock) void k_balance_flow(EvalArgs a) {
 // A wavefront owns 64 contingencies (one per lane) and BL consecutive
 // branches; its BL outage factors stay in registers.  A block stacks WL
 // wavefronts along l and covers the periods [t0, t0 + TC) (grid.z splits
-// the periods); its base flows F, reactive maxima qmax2 and the flows of its
-// 64 outaged branches are staged in LDS once.  For each (t, l) every lane
-// forms the post-outage flow P = F_tl + LODF_lk F_tk and tests
-// P^2 + qmax2_tl > s_ctg^2.  Only when some lane of the wavefront is
-// overloaded does it evaluate the soft-ReLU and its derivative and take the
-// wavefront sums over k (R: d/dF_tl, Q: d/dqmax2_tl); z_tk and S_tk (the
-// derivative through F_tk) accumulate in the lane over l and are summed over
-// the block's wavefronts in LDS.  The outaged branch itself and the padding
-// carry a NaN factor, so they never test overloaded.
+// the periods).  The branch quantities F_tl, qmax2_tl and s_ctg^2 are the
+// same for every lane, so they are read with scalar loads into SGPRs; the
+// flows of the block's 64 outaged branches are staged in LDS.  For each
+// period and group of 8 branches every lane forms the post-outage flows
+// P = F_tl + LODF_lk F_tk and tests P^2 + qmax2_tl > s_ctg^2 (one compare
+// into a ballot per branch).  Only a branch with an overloaded lane
+// evaluates soft-ReLUs and sums dP (-> R, d/dF_tl) and dq (-> Q,
+// d/dqmax2_tl) over its 64 lanes; the other branches store zero partials.
+// z_tk and S_tk (the derivative through F_tk) accumulate in the lane over l
+// and are summed over the block's wavefronts in LDS.  The outaged branch
+// itself and the padding carry a NaN factor, so they never test overloaded.
 
-template <int BL>
-__global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
-  extern __shared__ double dyn[];
+// LT: storage type of the outage factors (double, float, or BF16 bits);
+// R: arithmetic type (double with FP64 factors, float otherwise).
+template <int BL, typename LT>
+__global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restrict__ lodf) {
+  static_assert(BL % 8 == 0 && BL <= 32, "branches per wavefront");
+  typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
+  __shared__ double sFk[kCtgMaxTc][64];
   __shared__ double zsh[2][8][64];
   __shared__ double ssh[2][8][64];
   const DevProblem& p = a.p;
@@ -636,43 +764,44 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int WL = blockDim.x >> 6;
-  const int lspan = BL * WL;
   const int lb = blockIdx.x, kb = blockIdx.y;
   const int T = p.T, Lp = p.Lp, Kp = p.Kp;
   const int TC = a.tc;
   const int t0 = blockIdx.z * TC;
   const int nt = min(TC, T - t0);
-  const int lblk = lb * lspan;
-  const int lbase = __builtin_amdgcn_readfirstlane(lblk + wv * BL);
+  const int lbase = __builtin_amdgcn_readfirstlane(lb * BL * WL + wv * BL);
   const bool on = lbase < Lp;
   const int k = kb * 64 + lane;
-  // stage sFQ[t][l][2] = {F, qmax2} and sFk[t][64]
-  double* sFQ = dyn;
-  double* sFk = dyn + 2 * TC * lspan;
-  for (int e = threadIdx.x; e < nt * lspan; e += blockDim.x) {
-    const int tt = e / lspan, ll = e - tt * lspan;
-    const int l = lblk + ll;
-    double f = 0.0, q = 0.0;
-    if (l < Lp) {
-      f = w.F[(size_t)(t0 + tt) * Lp + l];
-      q = w.q2[(size_t)(t0 + tt) * Lp + l];
-    }
-    sFQ[2 * e] = f;
-    sFQ[2 * e + 1] = q;
-  }
   for (int e = threadIdx.x; e < nt * 64; e += blockDim.x) {
     const int tt = e >> 6, kk = e & 63;
-    sFk[e] = w.Fk[(size_t)(t0 + tt) * Kp + kb * 64 + kk];
+    sFk[tt][kk] = w.Fk[(size_t)(t0 + tt) * Kp + kb * 64 + kk];
   }
-  const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
-  const double eps2 = eps * eps;
-  double lod[BL], smx[BL], smx2[BL];
+  const cdouble* Sc = as_const(p.ctg_smax2);
+  const cdouble* Mc = as_const(p.ctg_smax);
+  const cdouble* Dc = as_const(p.dt);
+  const double beta = w.params[PB_BETA];
+  const R eps = (R)w.params[PB_EPS];
+  const R eps2 = eps * eps;
+  R lod[BL], smx2[BL];
+  // lane e of chunk c holds F and qmax2 of period t0 + e / 8, branch
+  // lbase + 8 c + e % 8 (TC * 8 <= 64 entries)
+  R fv[BL / 8], qv[BL / 8];
   if (on) {
 #pragma unroll
     for (int j = 0; j < BL; ++j) {
-      lod[j] = p.lodf[(size_t)(lbase + j) * Kp + k];
-      smx[j] = p.ctg_smax[lbase + j];
-      smx2[j] = p.ctg_smax2[lbase + j];
+      lod[j] = lodf_load(lodf, (size_t)(lbase + j) * Kp + k);
+      smx2[j] = (R)Sc[lbase + j];
+    }
+    const int et = lane >> 3, eg = lane & 7;
+#pragma unroll
+    for (int c = 0; c < BL / 8; ++c) {
+      fv[c] = R(0);
+      qv[c] = R(0);
+      if (et < nt) {
+        const size_t e = (size_t)(t0 + et) * Lp + lbase + c * 8 + eg;
+        fv[c] = (R)w.F[e];
+        qv[c] = (R)w.q2[e];
+      }
     }
   }
   __syncthreads();
@@ -683,39 +812,51 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a) {
   for (int u = 0; u < kCtgMaxTc; ++u) { zs[u] = 0.0; ss[u] = 0.0; }
   for (int tt = 0; tt < nt; ++tt) {
     const int t = t0 + tt;
-    double zacc = 0.0, sacc = 0.0, racc = 0.0, qacc = 0.0;
+    R zacc = R(0), sacc = R(0);
     if (on) {
-      const double kt = p.dt[t] * p.c_s * beta;
-      const double fk = sFk[tt * 64 + lane];
-      const double* fq = sFQ + 2 * (tt * lspan + wv * BL);
-      double Fv[BL], Qv[BL];
+      const R fk = (R)sFk[tt][lane];
+      const size_t o = ((size_t)kb * T + t) * Lp + lbase;
 #pragma unroll
-      for (int j = 0; j < BL; ++j) { Fv[j] = fq[2 * j]; Qv[j] = fq[2 * j + 1]; }
+      for (int c = 0; c < BL / 8; ++c) {
+        R Fr[8], Qr[8], P[8], s2[8];
 #pragma unroll
-      for (int j = 0; j < BL; ++j) {
-        const double P = fma(lod[j], fk, Fv[j]);
-        const double s2 = fma(P, P, Qv[j]);
-        const bool over = s2 > smx2[j];
-        if (__builtin_amdgcn_ballot_w64(over)) {
-          double dP = 0.0, dq = 0.0;
-          if (over) {
-            zacc += ctg_overload(P, s2, smx[j], eps, eps2, kt, dP, dq);
-            sacc += lod[j] * dP;
-          }
-          const double rs = wave_sum(dP);
-          const double qs = wave_sum(dq);
-          if (lane == j) { racc = rs; qacc = qs; }
+        for (int g = 0; g < 8; ++g) {
+          Fr[g] = readlane_any(fv[c], tt * 8 + g);
+          Qr[g] = readlane_any(qv[c], tt * 8 + g);
         }
-      }
-      if (lane < BL) {
-        const size_t o = ((size_t)kb * T + t) * Lp + lbase + lane;
-        w.rpart[o] = racc;
-        w.qpart[o] = qacc;
+        unsigned rows = 0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const int j = c * 8 + g;
+          P[g] = fma_uniform_c(lod[j], fk, Fr[g]);
+          s2[g] = fma_uniform_c(P[g], P[g], Qr[g]);
+          if (__builtin_amdgcn_ballot_w64(s2[g] > smx2[j])) rows |= 1u << g;
+        }
+        if (rows) {
+          const R kt = (R)(Dc[t] * p.c_s * beta);
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            if ((rows >> g) & 1u) {
+              const int j = c * 8 + g;
+              R dP = R(0), dq = R(0);
+              if (s2[g] > smx2[j]) {
+                zacc += ctg_overload(P[g], s2[g], (R)Mc[lbase + j], eps, eps2, kt, dP, dq);
+                sacc = fma(lod[j], dP, sacc);
+              }
+              const R r = pair_sum(dP, dq);
+              if ((lane & 31) == 0) (lane ? w.qpart : w.rpart)[o + j] = (double)r;
+            }
+          }
+        }
+        if (lane < 8 && !((rows >> lane) & 1u)) {
+          w.rpart[o + c * 8 + lane] = 0.0;
+          w.qpart[o + c * 8 + lane] = 0.0;
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < kCtgMaxTc; ++u)
-      if (u == tt) { zs[u] = zacc; ss[u] = sacc; }
+      if (u == tt) { zs[u] = (double)zacc; ss[u] = (double)sacc; }
   }
   // sum z and S over the block's wavefronts, one period at a time
 #pragma unroll
@@ -781,11 +922,10 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
 // outage-correction term S* = sum_l LODF_lk* dP_tlk* belongs to dL/dF at the
 // outaged branch and is applied in k_final as a rank-1 term (per-chunk sums).
 
-__global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
-  __shared__ double red[16];
+__device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
-  const int t = blockIdx.y, lc = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int T = p.T, L = p.L, K = p.K, Lp = p.Lp, Kp = p.Kp, Tp = p.Tp;
   const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
   const double kt = p.dt[t] * p.c_s * beta;
@@ -825,7 +965,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
       r *= invK;
       q *= invK;
       if (l != p.brk[kstar]) {
-        const double lo = p.lodf[(size_t)l * Kp + kstar];
+        const double lo = lodf_value(p, l, kstar);
         const double P = fma(lo, w.Fk[(size_t)t * Kp + kstar], Fl);
         const double s2 = fma(P, P, q2l);
         if (s2 > sm2) {
@@ -856,6 +996,17 @@ __global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
   }
   block_sum<1>(sacc, red);
   if (tid == 0) w.smaxp[(size_t)t * a.nLc + lc] = sacc[0];
+}
+
+// Blocks [0, nLc T): flow adjoints of (period, 256-branch chunk); then the
+// nb_bus power-balance blocks, which only need the forward flows.
+__global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
+  __shared__ double smem[2 * kSegChunk + 16];
+  const int b = blockIdx.x, nasm = a.nLc * a.p.T;
+  if (b < nasm)
+    ctg_assemble(a, b / a.nLc, b % a.nLc, smem);
+  else
+    bus_balance(a, b - nasm, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1086,9 +1237,14 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const double* x, size_t
 // ---------------------------------------------------------------------------
 // launchers
 
-size_t ctg_dyn_lds(const Problem* pr) {
-  const int lspan = pr->tile.bl * pr->tile.wl;
-  return (size_t)pr->tile.tc * (2 * lspan + kCtgLanes) * sizeof(double);
+template <typename LT>
+void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArgs& a,
+                     const LT* lodf) {
+  switch (bl) {
+    case 8: hipLaunchKernelGGL((k_ctg_main<8, LT>), grid, block, 0, s, a, lodf); break;
+    case 16: hipLaunchKernelGGL((k_ctg_main<16, LT>), grid, block, 0, s, a, lodf); break;
+    default: hipLaunchKernelGGL((k_ctg_main<32, LT>), grid, block, 0, s, a, lodf); break;
+  }
 }
 
 int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* grad,
@@ -1120,30 +1276,26 @@ int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* gr
     if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[i]), s);
   };
   rec(0);
-  hipLaunchKernelGGL(k_forward, dim3(pr->nb_br + pr->T), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_forward, dim3(pr->nb_br + pr->T + pr->Lp / 16), dim3(kBlock), 0, s, a);
   rec(1);
-  hipLaunchKernelGGL(k_balance_flow, dim3(pr->nb_bus + pr->Lp / 16), dim3(kBlock), 0, s, a);
-  rec(2);
   if (pr->K > 0) {
     const int ntc = (pr->T + pr->tile.tc - 1) / pr->tile.tc;
     const dim3 grid(pr->nLb, pr->nKb, ntc), block(64 * pr->tile.wl);
-    const size_t lds = ctg_dyn_lds(pr);
-    switch (pr->tile.bl) {
-      case 8: hipLaunchKernelGGL(k_ctg_main<8>, grid, block, lds, s, a); break;
-      case 16: hipLaunchKernelGGL(k_ctg_main<16>, grid, block, lds, s, a); break;
-      default: hipLaunchKernelGGL(k_ctg_main<32>, grid, block, lds, s, a); break;
-    }
+    const DevProblem& dp = pr->dp;
+    if (dp.lodf_kind == kLodfF64) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf);
+    else if (dp.lodf_kind == kLodfF32) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf32);
+    else launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf16);
   }
-  rec(3);
+  rec(2);
   if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(pr->nKc, pr->T), dim3(64), 0, s, a);
+  rec(3);
+  hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0, s, a);
   rec(4);
-  hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc, pr->T), dim3(kBlock), 0, s, a);
-  rec(5);
   hipLaunchKernelGGL(k_adjoint, dim3(pr->G16 / 16 * pr->nsplit + pr->nb_br), dim3(kBlock), 0, s,
                      a);
-  rec(6);
+  rec(5);
   hipLaunchKernelGGL(k_final, dim3(pr->nb_bus + pr->nb_gen + 1), dim3(kBlock), 0, s, a);
-  rec(7);
+  rec(6);
   return (int)hipGetLastError();
 }
 

@@ -34,8 +34,9 @@ QG_NCLASS = 6
 QG_NKERNELS = 8
 QG_CTG_ALL_NONBRIDGE, QG_CTG_LIST = 0, 1
 QG_FLAG_CHECK_FINITE = 0x1
-KERNEL_NAMES = ("k_forward", "k_balance_flow", "k_ctg_main", "k_ctg_zred", "k_ctg_asm",
-                "k_adjoint", "k_final")
+QG_FLAG_CTG_FP32 = 0x2
+QG_FLAG_CTG_BF16 = 0x4
+KERNEL_NAMES = ("k_forward", "k_ctg_main", "k_ctg_zred", "k_ctg_asm", "k_adjoint", "k_final")
 
 _pd = C.POINTER(C.c_double)
 _pi = C.POINTER(C.c_int32)
@@ -221,10 +222,10 @@ def qg_ctg_list(h, k):
 
 
 def qg_problem_dims(h):
-    out = np.zeros(16, dtype=np.int32)
-    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 16), "qg_problem_dims")
+    out = np.zeros(17, dtype=np.int32)
+    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 17), "qg_problem_dims")
     keys = ("N", "L", "G", "T", "M", "K", "Lp", "Kp", "G16", "G4", "Tp", "nLb", "nKb",
-            "ctg_bl", "ctg_wl", "ctg_tc")
+            "ctg_bl", "ctg_wl", "ctg_tc", "lodf_kind")
     return dict(zip(keys, (int(v) for v in out)))
 
 

@@ -105,3 +105,20 @@ def test_parallel_branches_are_not_bridges():
 
 def test_null_arguments():
     _expect(qg.QG_ERR_ARG, lambda: qg.qg_problem_sizes(qg.qg_grid_desc(), qg.qg_build_opts()))
+
+
+def test_precision_flags_size_the_factor_storage():
+    c = synth.config_case("c2")
+    lp = (c.n_branch + 63) // 64 * 64
+    kp = (c.n_ctg + 63) // 64 * 64
+    s64 = _sizes(c).const_bytes
+    s32 = _sizes(c, flags=qg.QG_FLAG_CTG_FP32).const_bytes
+    s16 = _sizes(c, flags=qg.QG_FLAG_CTG_BF16).const_bytes
+    # the factor array shrinks from 8 to 4 to 2 bytes per entry (256-B aligned)
+    assert abs((s64 - s32) - 4 * lp * kp) <= 256
+    assert abs((s32 - s16) - 2 * lp * kp) <= 256
+    with pytest.raises(qg.QgError) as e:
+        _sizes(c, flags=qg.QG_FLAG_CTG_FP32 | qg.QG_FLAG_CTG_BF16)
+    assert e.value.status == qg.QG_ERR_ARG
+    with pytest.raises(qg.QgError):
+        _sizes(c, flags=0x100)

@@ -93,6 +93,17 @@ def test_terms_and_gradient_c2(qg, which):
     assert_grad_close(c, g, gr)
 
 
+def test_terms_and_gradient_c3(qg):
+    """The 2,000-bus, 48-period grid with its 2,410 contingencies, every output."""
+    c = case("c3")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, 7, spread=0.3)
+    t, g = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+
+
 def test_intermediates_c2(qg):
     """Base-case DC flows, reactive maxima, balance multipliers and the
     per-contingency penalties z_tk against the oracle's own algebra."""
@@ -250,6 +261,29 @@ def test_graph_replay_equals_eager(qg):
     for a, b in zip(outs[0][:3], outs[1][:3]):
         assert np.array_equal(a, b)
     assert outs[0][3] == outs[1][3]
+
+
+def test_graph_recaptured_after_tile_change(qg):
+    """A cached step graph is not reused once the contingency tile changes:
+    graph and eager solves under the new tile agree bit for bit."""
+    import torch
+    c = case("c2")
+    prob = qg.Problem(c)
+    x0 = synth.flat_start(c)
+    opts = dict(alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3)
+    xd, md, vd = prob.new_vector(x0), prob.new_vector(), prob.new_vector()
+    prob.solve(xd, md, vd, qg.solve_opts(8, [1e-3] * 6, use_graph=1, **opts))
+    prob.set_ctg_tile(16, 4, 5)
+    outs = []
+    for use_graph in (1, 0):
+        # the same buffers, so only the tile tells the two captures apart
+        xd.copy_(torch.from_numpy(x0).to(xd.device))
+        md.zero_()
+        vd.zero_()
+        prob.solve(xd, md, vd, qg.solve_opts(8, [1e-3] * 6, use_graph=use_graph, **opts))
+        torch.cuda.synchronize()
+        outs.append(xd.cpu().numpy().copy())
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_no_contingency_grid(qg):
