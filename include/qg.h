@@ -275,7 +275,7 @@ qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
  * workspace into host memory (synchronises the stream).  Names and shapes
  * (row-major, padded sizes from qg_problem_dims):
  *   "F" [T][Lp] base-case DC flows      "Fk" [T][Kp] flows of outaged branches
- *   "q2" [T][Lp] max(q_fr^2, q_to^2)    "psum" [T] total generator output
+ *   "q2" [T][Lp] max(q_fr^2, q_to^2)
  *   "lamp", "lamq" [T][N] balance multipliers
  *   "zval" [T][Kp] contingency penalties z_tk
  *   "gfT" [Lp][Tp] dL/dF                "qtot" [T][Lp] dL/d max(q^2)
@@ -286,6 +286,18 @@ qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
  */
 qg_status qg_debug_fetch(const qg_problem* prob, const void* d_workspace, const char* name,
                          void* host, size_t bytes, void* stream);
+
+/*
+ * Measurement support: mean duration (microseconds, written to *mean_us) of
+ * one kernel of the step, stage 0..5 in stream order (k_forward, k_ctg_main,
+ * k_ctg_zred, k_ctg_asm, k_adjoint, k_final), launched reps times back to back
+ * on the stream after one full evaluation at x (homotopy h) has produced its
+ * inputs; each of these launches recomputes the same outputs.  Synchronises
+ * the stream.  Errors: ARG (stage, reps outside [1, 100000], pointers),
+ * DEVICE.
+ */
+qg_status qg_time_stage(qg_problem* prob, const double* d_x, const qg_homotopy* h, int32_t stage,
+                        int32_t reps, void* d_workspace, void* stream, double* mean_us);
 
 void qg_destroy_problem(qg_problem* prob);
 const char* qg_status_string(qg_status s);

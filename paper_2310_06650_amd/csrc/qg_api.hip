@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include <new>
 
 #include "qg_internal.h"
@@ -139,7 +140,7 @@ qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl, int32_t tc) {
     return fail(QG_ERR_ARG, "tile must have bl in {8,16,32}, wl in {1,2,4,8}, bl*wl >= 16");
   qg::Problem& p = pr->p;
   const int span = bl * wl;
-  if (tc <= 0) tc = qg::default_ctg_tc(p.T, span);
+  if (tc <= 0) tc = qg::default_ctg_tc(p);
   if (tc > p.T) tc = p.T;
   if (tc > qg::kCtgMaxTc) return fail(QG_ERR_ARG, "at most 8 periods per block");
   p.tile = qg::CtgTile{bl, wl, tc};
@@ -177,6 +178,32 @@ qg_status qg_eval_grad(qg_problem* pr, const double* d_x, double* d_grad, double
   m.rho_s = h->rho_scale;
   int e = qg::launch_eval(&p, w, d_x, d_grad, d_terms, m, 0, nullptr, nullptr, stream, nullptr);
   if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+  return QG_OK;
+}
+
+qg_status qg_time_stage(qg_problem* pr, const double* d_x, const qg_homotopy* h, int32_t stage,
+                        int32_t reps, void* d_workspace, void* stream, double* mean_us) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d_x || !h || !d_workspace || !mean_us) return fail(QG_ERR_ARG, "null argument");
+  if (!aligned(d_x) || !aligned(d_workspace))
+    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+  if (stage < 0 || stage >= qg::kStages) return fail(QG_ERR_ARG, "stage out of range");
+  if (reps < 1 || reps > 100000) return fail(QG_ERR_ARG, "reps must be in [1, 100000]");
+  if (!(h->eps >= 0.0) || !(h->beta >= 0.0) || !(h->rho_scale >= 0.0) || !std::isfinite(h->eps) ||
+      !std::isfinite(h->beta) || !std::isfinite(h->rho_scale))
+    return fail(QG_ERR_ARG, "homotopy values must be finite and non-negative");
+  const qg::Problem& p = pr->p;
+  qg::DevWork w = qg::carve_workspace(&p, d_workspace);
+  qg::EvalMode m{};
+  m.schedule = 0;
+  m.eps = h->eps;
+  m.beta = h->beta;
+  m.rho_s = h->rho_scale;
+  double ms = 0.0;
+  int e = qg::time_stage(&p, w, d_x, m, stage, reps, stream, &ms);
+  if (e != 0) return hip_fail((hipError_t)e, "stage timing");
+  *mean_us = ms * 1e3;
   return QG_OK;
 }
 
@@ -284,10 +311,14 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
 
   const bool profile = o->profile != 0;
   const bool graph = o->use_graph != 0 && !profile;
-  hipEvent_t evs[QG_NKERNELS];
-  constexpr int kKernels = 6;
-  if (profile)
-    for (int i = 0; i <= kKernels; ++i) HIP_TRY(hipEventCreate(&evs[i]), "event");
+  // profile: events around every kernel of up to kProfSteps queued steps,
+  // read after one synchronisation, so host latency does not enter the times
+  constexpr int kKernels = qg::kStages, kProfSteps = 32, kEv = kKernels + 1;
+  std::vector<hipEvent_t> evs;
+  if (profile) {
+    evs.resize(kProfSteps * kEv);
+    for (auto& e : evs) HIP_TRY(hipEventCreate(&e), "event");
+  }
 
   // graph of gsteps consecutive steps (the step counter lives on the device);
   // one graph launch costs about as much as several kernels, so it covers
@@ -330,19 +361,30 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
         left -= gsteps;
       }
     }
-    for (int64_t k = 0; k < left; ++k) {
-      int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, ex,
-                              profile ? reinterpret_cast<void**>(evs) : nullptr);
-      if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
-      if (profile) {
-        HIP_TRY(hipEventSynchronize(evs[kKernels]), "event sync");
-        for (int q = 0; q < kKernels; ++q) {
-          float ms = 0.f;
-          HIP_TRY(hipEventElapsedTime(&ms, evs[q], evs[q + 1]), "elapsed");
-          rep->kernel_ms[q] += ms;
-          rep->kernel_calls[q] += 1;
+    if (profile) {
+      for (int64_t k = 0; k < left;) {
+        const int nb = (int)std::min<int64_t>(kProfSteps, left - k);
+        for (int st = 0; st < nb; ++st) {
+          int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, ex,
+                                  reinterpret_cast<void**>(&evs[st * kEv]));
+          if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
         }
+        HIP_TRY(hipEventSynchronize(evs[(nb - 1) * kEv + kKernels]), "event sync");
+        for (int st = 0; st < nb; ++st)
+          for (int q = 0; q < kKernels; ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, evs[st * kEv + q], evs[st * kEv + q + 1]),
+                    "elapsed");
+            rep->kernel_ms[q] += ms;
+            rep->kernel_calls[q] += 1;
+          }
+        k += nb;
       }
+      return QG_OK;
+    }
+    for (int64_t k = 0; k < left; ++k) {
+      int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, ex, nullptr);
+      if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
     }
     return QG_OK;
   };
@@ -393,7 +435,7 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   if (profile) {
     for (int q = 0; q < kKernels; ++q)
       if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
-    for (int i = 0; i <= kKernels; ++i) (void)hipEventDestroy(evs[i]);
+    for (auto& e : evs) (void)hipEventDestroy(e);
   }
   return QG_OK;
 }
@@ -409,7 +451,7 @@ qg_status qg_debug_fetch(const qg_problem* pr, const void* d_workspace, const ch
   struct Item { const char* n; const void* ptr; size_t bytes; };
   const Item items[] = {
       {"F", w.F, (size_t)p.T * p.Lp * D},       {"Fk", w.Fk, (size_t)p.T * p.Kp * D},
-      {"q2", w.q2, (size_t)p.T * p.Lp * D},     {"psum", w.psum, (size_t)p.T * D},
+      {"q2", w.q2, (size_t)p.T * p.Lp * D},
       {"lamp", w.lamp, (size_t)p.T * p.N * D},  {"lamq", w.lamq, (size_t)p.T * p.N * D},
       {"zval", w.zval, (size_t)p.T * p.Kp * D}, {"gfT", w.gfT, (size_t)p.Lp * p.Tp * D},
       {"gpdc", w.gpdc, (size_t)p.nsplit * p.T * p.G16 * D},

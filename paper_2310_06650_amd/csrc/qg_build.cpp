@@ -155,7 +155,6 @@ WorkLayout work_layout(const Problem& p) {
       T * twoL * D, T * twoL * D,                       // epP, epQ
       9 * T * L * D,                                    // bco
       T * p.Lp * D,                                     // q2
-      T * D,                                            // psum
       T * p.Lp * D, T * p.Kp * D,                       // F, Fk
       T * N * D, T * N * D,                             // lamp, lamq
       4 * T * G * D,                                    // gdev
@@ -187,13 +186,15 @@ WorkLayout work_layout(const Problem& p) {
 
 }  // namespace
 
-int default_ctg_tc(int T, int lspan) {
-  // periods per block of the contingency map-reduce: enough blocks to give
-  // the chip several wavefronts per SIMD
-  (void)lspan;
-  int tc = std::min(T, kCtgMaxTc);
-  if (T > 8) tc = std::min(tc, (T + 2) / 3);
-  return std::max(1, tc);
+int default_ctg_tc(const Problem& p) {
+  // periods per block of the contingency map-reduce.  Short chunks give the
+  // chip more blocks and shorter per-block tails, but every chunk re-reads
+  // the outage factors: take 2 periods while the re-reads stay within a
+  // 64 MB budget per step, else the longest chunk (8 periods).
+  const double lodf_bytes = (double)p.Lp * p.Kp * lodf_elem_bytes(lodf_kind_of(p.flags));
+  const int chunks2 = (p.T + 1) / 2;
+  int tc = (lodf_bytes * chunks2 <= 64.0 * (1 << 20)) ? 2 : kCtgMaxTc;
+  return std::max(1, std::min(tc, p.T));
 }
 
 qg_status fail(qg_status s, const std::string& msg) {
@@ -293,7 +294,8 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   }
   p->nKc = p->Kp / kCtgLanes;
   p->nLc = (p->Lp + kBlock - 1) / kBlock;
-  p->tile = CtgTile{8, 8, default_ctg_tc(T, 8 * 8)};
+  p->tile = CtgTile{8, 8, 0};
+  p->tile.tc = default_ctg_tc(*p);
   p->nLb_max = p->Lp / 16;
   p->nKb_max = p->Kp / kCtgLanes;
   p->nLb = p->Lp / (p->tile.bl * p->tile.wl);
@@ -518,9 +520,12 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
   });
   Yinv.clear();
   Yinv.shrink_to_fit();
-  // ---- the ISF restricted to generator buses, its row sums and the load term:
-  // F_t = ISF p_bar_t = ISF[:, bus(j)] p_t - ISF load_t - mean_t ISF 1, and the
-  // slack-corrected injection gradient (eq. (correction)) of generator j is
+  // ---- the ISF restricted to generator buses, its row sums and the load term.
+  // With the uniform slack, F_t = ISF p_bar_t = ISF[:, bus(j)] p_t - ISF load_t
+  // - mean_t ISF 1 and mean_t = (sum_j p_tj - sum_i load_ti) / N, so
+  // F_tl = sum_j p_tj (ISF[l][bus(j)] - rsum_l / N) - c_tl with the per-grid
+  // constant c_tl = ISF load_t - rsum_l sum_i load_ti / N; the slack-corrected
+  // injection gradient (eq. (correction)) of generator j is the transpose:
   // sum_l dL/dF_tl (ISF[l][bus(j)] - rsum_l / N).
   {
     std::vector<double> rsum(Lp, 0.0);
@@ -535,7 +540,7 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
       const int bj = d->gen_bus[j];
       for (int l = 0; l < L; ++l) {
         const double v = isf[(size_t)l * Np + bj];
-        gT[(size_t)j * Lp + l] = v;
+        gT[(size_t)j * Lp + l] = v - rsum[l] / (double)N;
         ga[(size_t)l * G16 + j] = v - rsum[l] / (double)N;
       }
     }
@@ -546,7 +551,7 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
         const double* row = &isf[(size_t)l * Np];
         double s = 0.0;
         for (int i = 0; i < N; ++i) s += row[i] * ld[i];
-        cl_[(size_t)t * Lp + l] = s;
+        cl_[(size_t)t * Lp + l] = s - rsum[l] * sum_load[t] / (double)N;
       }
     });
     put(img, cl.off[45], rsum.data(), Lp);
@@ -636,13 +641,13 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   w.params = D(0);
   w.step = reinterpret_cast<int64_t*>(base + wl.off[1]);
   w.sched = D(2);
-  w.epP = D(3); w.epQ = D(4); w.bco = D(5); w.q2 = D(6); w.psum = D(7);
-  w.F = D(8); w.Fk = D(9); w.lamp = D(10); w.lamq = D(11); w.gdev = D(12);
-  w.zpart = D(13); w.spart = D(14); w.rpart = D(15); w.qpart = D(16);
-  w.smean = D(17); w.zval = D(18); w.gfT = D(19); w.qtot = D(20); w.gpdc = D(21);
-  w.epGV = D(22); w.epGT = D(23); w.tpart = D(24); w.terms = D(25);
-  w.drs = D(26); w.zmaxp = D(27); w.zargp = D(28); w.zsump = D(29); w.kstar = D(30);
-  w.smaxp = D(31);
+  w.epP = D(3); w.epQ = D(4); w.bco = D(5); w.q2 = D(6);
+  w.F = D(7); w.Fk = D(8); w.lamp = D(9); w.lamq = D(10); w.gdev = D(11);
+  w.zpart = D(12); w.spart = D(13); w.rpart = D(14); w.qpart = D(15);
+  w.smean = D(16); w.zval = D(17); w.gfT = D(18); w.qtot = D(19); w.gpdc = D(20);
+  w.epGV = D(21); w.epGT = D(22); w.tpart = D(23); w.terms = D(24);
+  w.drs = D(25); w.zmaxp = D(26); w.zargp = D(27); w.zsump = D(28); w.kstar = D(29);
+  w.smaxp = D(30);
   return w;
 }
 

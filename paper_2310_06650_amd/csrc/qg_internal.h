@@ -59,9 +59,9 @@ struct DevProblem {
   const double* load_p; const double* load_q;  // [T*N]
   const double* dt; const double* rsv_req; const double* sum_load;  // [T]
   // sensitivities, restricted to generator buses
-  const double* isf_gT;  // [G4][Lp]  ISF[l][bus(j)], zero padded (B of the flow product)
+  const double* isf_gT;  // [G4][Lp]  ISF[l][bus(j)] - rsum[l]/N, zero padded (B of the flow product)
   const double* isf_ga;  // [Lp][G16] ISF[l][bus(j)] - rsum[l]/N (B of the adjoint product)
-  const double* cload;   // [T][Lp]   sum_i ISF[l][i] load_p[t][i]
+  const double* cload;   // [T][Lp]   sum_i ISF[l][i] load_p[t][i] - rsum[l] sum_load[t] / N
   const double* rsum;    // [Lp]      sum_i ISF[l][i]
   const double* lodf;    // [Lp][Kp]  outage factors; NaN marks (k,k) and padding
   const float* lodf32;   //           the same in FP32 (QG_FLAG_CTG_FP32)
@@ -79,7 +79,6 @@ struct DevWork {
   double* epP; double* epQ;      // [T][2L] branch flows at bus-sorted endpoint slots
   double* bco;         // [9][T][L] per-branch reverse coefficients
   double* q2;          // [T][Lp]  max(q_fr^2, q_to^2)
-  double* psum;        // [T]      sum_j p_tj
   double* F;           // [T][Lp]  base-case DC flows
   double* Fk;          // [T][Kp]  flows of the outaged branches
   double* lamp; double* lamq;    // [T][N] balance multipliers
@@ -171,12 +170,17 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
                       HostBuild* hb);
 void rebase_pointers(Problem* p, void* arena);
 DevWork carve_workspace(const Problem* p, void* ws);
-int default_ctg_tc(int T, int lspan);
+int default_ctg_tc(const Problem& p);
 
-// Kernel launchers (qg_kernels.hip).
+// Kernel launchers (qg_kernels.hip).  A step is kStages kernels.
+constexpr int kStages = 6;
 int launch_eval(const Problem* p, const DevWork& w, const double* x, double* grad,
                 double* terms_out, const EvalMode& mode, int fuse_adam, double* m,
                 double* v, void* stream, void** events /* nullable [QG_NKERNELS] */);
+// Mean duration of one kernel of the step (0..kStages-1), launched reps times
+// back to back after a full evaluation at x has produced its inputs.
+int time_stage(const Problem* p, const DevWork& w, const double* x, const EvalMode& mode,
+               int stage, int reps, void* stream, double* mean_ms);
 int launch_adam(const Problem* p, double* x, double* m, double* v, const double* g,
                 const double lr[QG_NCLASS], double bc1, double bc2, double b1,
                 double b2, double eps, int eps_in_num, void* stream);

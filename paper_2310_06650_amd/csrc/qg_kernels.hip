@@ -626,42 +626,27 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
 constexpr int kSlabLds = 4 * 4 * 256;
 static_assert(kSlabLds >= 2 * kSegChunk + 8 * kBlock, "LDS carve");
 
-// Base-case DC flows of 16 branches for every period, on FP64 MFMA:
-// F[t][l] = sum_j p_tj ISF[l][bus(j)] - ISF load_t - mean_t rowsum_l, with
-// mean_t = (sum_j p_tj - sum_i load_ti) / N the uniform slack; also the
-// outaged branches' flows.  The block first sums each period's output itself
-// (a fixed order, so every slab sees the same mean).
+// Base-case DC flows of 16 branches for every period, on FP64 MFMA, with the
+// uniform slack folded into the operand: F[t][l] = sum_j p_tj (ISF[l][bus(j)]
+// - rowsum_l / N) - c[t][l], where the per-grid constant c holds the loads'
+// part (ISF load_t - rowsum_l sum_i load_ti / N).  Also the outaged branches'
+// flows.
 __device__ void flow_slab(const EvalArgs& a, int slab, double* smem) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int T = p.T, G = p.G, Lp = p.Lp, Kp = p.Kp, N = p.N;
   const double* xP = a.x + 2 * (size_t)T * N;
-  double* ps = smem + kSlabLds;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int t = wv; t < T; t += kBlock / 64) {
-    double sum = 0.0;
-    for (int j = lane; j < G; j += 64) sum += xP[(size_t)t * G + j];
-    sum = wave_sum(sum);
-    if (lane == 0) {
-      ps[t] = sum;
-      if (slab == 0) w.psum[t] = sum;
-    }
-  }
-  __syncthreads();
   const int n0 = slab * 16;
   double* F = w.F;
   double* Fk = w.Fk;
   const int* kof = p.kof;
   const double* cload = p.cload;
-  const double* rsum = p.rsum;
-  const double* sum_load = p.sum_load;
   auto aload = [=](int k, int row) -> double {
     return (row < T && k < G) ? xP[(size_t)row * G + k] : 0.0;
   };
   auto epi = [=](int row, int col, double v) {
     if (row < T) {
-      const double mean = (ps[row] - sum_load[row]) / (double)N;
-      const double f = (v - cload[(size_t)row * Lp + col]) - mean * rsum[col];
+      const double f = v - cload[(size_t)row * Lp + col];
       F[(size_t)row * Lp + col] = f;
       const int k = kof[col];
       if (k >= 0) Fk[(size_t)row * Kp + k] = f;
@@ -673,7 +658,7 @@ __device__ void flow_slab(const EvalArgs& a, int slab, double* smem) {
 // Blocks [0, nb_br): branch forward; [nb_br, nb_br + T): one period each;
 // then Lp / 16 flow slabs.
 __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
-  __shared__ double smem[kSlabLds + kMaxT];
+  __shared__ double smem[kSlabLds];
   StepParams sp;
   resolve_params(a, sp);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -948,16 +933,28 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   }
   double sacc[1] = {0.0};
   if (K > 0) {
-    // worst contingency of the period from the per-chunk partials (chunk order)
-    double zmax = w.zmaxp[(size_t)t * a.nKc];
-    int kstar = (int)w.zargp[(size_t)t * a.nKc];
-    double zsum = w.zsump[(size_t)t * a.nKc];
-    for (int c = 1; c < a.nKc; ++c) {
-      const size_t o = (size_t)t * a.nKc + c;
-      const double v = w.zmaxp[o];
-      const int i = (int)w.zargp[o];
-      if (better(v, i, zmax, kstar)) { zmax = v; kstar = i; }
-      zsum += w.zsump[o];
+    // worst contingency of the period from the per-chunk partials (chunk
+    // order), 16 chunks' loads in flight at a time
+    double zmax = -DBL_MAX, zsum = 0.0;
+    int kstar = INT_MAX;
+    const size_t ob = (size_t)t * a.nKc;
+    for (int c0 = 0; c0 < a.nKc; c0 += 16) {
+      double vz[16], vi[16], vs[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const bool in = c0 + u < a.nKc;
+        vz[u] = in ? w.zmaxp[ob + c0 + u] : -DBL_MAX;
+        vi[u] = in ? w.zargp[ob + c0 + u] : (double)INT_MAX;
+        vs[u] = in ? w.zsump[ob + c0 + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (c0 + u < a.nKc) {
+          const int i = (int)vi[u];
+          if (better(vz[u], i, zmax, kstar)) { zmax = vz[u]; kstar = i; }
+          zsum += vs[u];
+        }
+      }
     }
     if (!(kstar >= 0 && kstar < K)) kstar = 0;  // NaN penalties: keep every index in range
     const double invK = 1.0 / (double)K;
@@ -1247,10 +1244,9 @@ void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArg
   }
 }
 
-int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* grad,
-                double* terms_out, const EvalMode& mode, int fuse_adam, double* m, double* v,
-                void* stream, void** events) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
+static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, double* grad,
+                          double* terms_out, const EvalMode& mode, int fuse_adam, double* m,
+                          double* v) {
   EvalArgs a;
   a.p = pr->dp;
   a.w = w;
@@ -1272,30 +1268,75 @@ int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* gr
   a.nLc = pr->nLc;
   a.tc = pr->tile.tc;
   a.toff = pr->toff;
-  auto rec = [&](int i) {
-    if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[i]), s);
-  };
-  rec(0);
-  hipLaunchKernelGGL(k_forward, dim3(pr->nb_br + pr->T + pr->Lp / 16), dim3(kBlock), 0, s, a);
-  rec(1);
-  if (pr->K > 0) {
-    const int ntc = (pr->T + pr->tile.tc - 1) / pr->tile.tc;
-    const dim3 grid(pr->nLb, pr->nKb, ntc), block(64 * pr->tile.wl);
-    const DevProblem& dp = pr->dp;
-    if (dp.lodf_kind == kLodfF64) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf);
-    else if (dp.lodf_kind == kLodfF32) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf32);
-    else launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf16);
+  return a;
+}
+
+// One kernel of the step, in stream order 0..kStages-1.
+static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStream_t s) {
+  switch (stage) {
+    case 0:
+      hipLaunchKernelGGL(k_forward, dim3(pr->nb_br + pr->T + pr->Lp / 16), dim3(kBlock), 0, s, a);
+      break;
+    case 1:
+      if (pr->K > 0) {
+        const int ntc = (pr->T + pr->tile.tc - 1) / pr->tile.tc;
+        const dim3 grid(pr->nLb, pr->nKb, ntc), block(64 * pr->tile.wl);
+        const DevProblem& dp = pr->dp;
+        if (dp.lodf_kind == kLodfF64) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf);
+        else if (dp.lodf_kind == kLodfF32) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf32);
+        else launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf16);
+      }
+      break;
+    case 2:
+      if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(pr->nKc, pr->T), dim3(64), 0, s, a);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0, s, a);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_adjoint, dim3(pr->G16 / 16 * pr->nsplit + pr->nb_br), dim3(kBlock), 0,
+                         s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(k_final, dim3(pr->nb_bus + pr->nb_gen + 1), dim3(kBlock), 0, s, a);
+      break;
   }
-  rec(2);
-  if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(pr->nKc, pr->T), dim3(64), 0, s, a);
-  rec(3);
-  hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0, s, a);
-  rec(4);
-  hipLaunchKernelGGL(k_adjoint, dim3(pr->G16 / 16 * pr->nsplit + pr->nb_br), dim3(kBlock), 0, s,
-                     a);
-  rec(5);
-  hipLaunchKernelGGL(k_final, dim3(pr->nb_bus + pr->nb_gen + 1), dim3(kBlock), 0, s, a);
-  rec(6);
+}
+
+int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* grad,
+                double* terms_out, const EvalMode& mode, int fuse_adam, double* m, double* v,
+                void* stream, void** events) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const EvalArgs a = make_args(pr, w, x, grad, terms_out, mode, fuse_adam, m, v);
+  for (int i = 0; i < kStages; ++i) {
+    if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[i]), s);
+    launch_stage(pr, a, i, s);
+  }
+  if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[kStages]), s);
+  return (int)hipGetLastError();
+}
+
+int time_stage(const Problem* pr, const DevWork& w, const double* x, const EvalMode& mode,
+               int stage, int reps, void* stream, double* mean_ms) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const EvalArgs a = make_args(pr, w, x, nullptr, nullptr, mode, 0, nullptr, nullptr);
+  for (int i = 0; i < kStages; ++i) launch_stage(pr, a, i, s);  // inputs of every stage
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return (int)err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) { (void)hipEventDestroy(e0); return (int)err; }
+  launch_stage(pr, a, stage, s);  // warm
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) launch_stage(pr, a, stage, s);
+  (void)hipEventRecord(e1, s);
+  err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return (int)err;
+  *mean_ms = (double)ms / reps;
   return (int)hipGetLastError();
 }
 

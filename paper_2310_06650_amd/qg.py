@@ -22,6 +22,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first "
         "(python -m paper_2310_06650_amd.build)")
+# PyTorch ships its own HIP runtime under the same soname as the system one.
+# Importing it first makes the library bind to that runtime, so one process
+# holds a single HIP runtime whichever module is imported first.
+import torch as _torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------- constants
@@ -112,6 +117,8 @@ _sig = {
     "qg_layout_of": (C.c_int, [_vp, C.POINTER(qg_layout)]),
     "qg_ctg_list": (C.c_int, [_vp, _pi, C.c_int32]),
     "qg_problem_dims": (C.c_int, [_vp, _pi, C.c_int32]),
+    "qg_time_stage": (C.c_int, [_vp, _vp, C.POINTER(qg_homotopy), C.c_int32, C.c_int32, _vp,
+                                _vp, C.POINTER(C.c_double)]),
     "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "qg_eval_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp, _vp]),
     "qg_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double * QG_NCLASS,
@@ -238,6 +245,13 @@ def qg_eval_grad(h, d_x, d_grad, d_terms, hom, d_ws, stream):
            "qg_eval_grad")
 
 
+def qg_time_stage(h, d_x, hom, stage, reps, d_ws, stream):
+    out = C.c_double(0.0)
+    _check(lib.qg_time_stage(h, d_x, C.byref(hom), int(stage), int(reps), d_ws, stream,
+                             C.byref(out)), "qg_time_stage")
+    return out.value
+
+
 def qg_adam_step(h, d_x, d_m, d_v, d_g, it, lr, cfg, stream):
     arr = (C.c_double * QG_NCLASS)(*[float(a) for a in lr])
     _check(lib.qg_adam_step(h, d_x, d_m, d_v, d_g, int(it), arr, C.byref(cfg), stream),
@@ -325,6 +339,13 @@ class Problem:
         if host is not None:
             t.copy_(self.torch.as_tensor(np.asarray(host, dtype=np.float64)))
         return t
+
+    def time_stage(self, x, stage, reps, eps, beta=1.0, rho_scale=1.0):
+        """Mean microseconds of one kernel of the step (index into KERNEL_NAMES)."""
+        if isinstance(stage, str):
+            stage = KERNEL_NAMES.index(stage)
+        return qg_time_stage(self.handle, x.data_ptr(), qg_homotopy(eps, beta, rho_scale), stage,
+                             reps, self.workspace.data_ptr(), self._stream())
 
     def eval_grad(self, x, eps, beta=1.0, rho_scale=1.0, grad=True):
         torch = self.torch

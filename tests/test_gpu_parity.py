@@ -320,3 +320,20 @@ def test_misaligned_buffer_rejected(qg):
         qg.qg_eval_grad(prob.handle, buf.data_ptr() + 8, None, None, qg.qg_homotopy(1e-2, 1, 1),
                         prob.workspace.data_ptr(), prob._stream())
     assert e.value.status == qg.QG_ERR_ARG
+
+
+def test_time_stage_leaves_results_unchanged(qg):
+    """Stage timing relaunches kernels whose outputs depend only on their
+    inputs: the evaluation afterwards is bitwise the same as before."""
+    c = case("c2")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, 12, spread=0.3)
+    t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    xd = prob.new_vector(x)
+    for i, name in enumerate(qg.KERNEL_NAMES):
+        us = prob.time_stage(xd, i, 5, 1e-2)
+        assert 0.0 < us < 1e5, (name, us)
+    t2, g2 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    assert np.array_equal(t1, t2) and np.array_equal(g1, g2)
+    with pytest.raises(qg.QgError):
+        prob.time_stage(xd, 6, 5, 1e-2)
