@@ -140,9 +140,11 @@ qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl, int32_t tc) {
     return fail(QG_ERR_ARG, "tile must have bl in {8,16,32}, wl in {1,2,4,8}, bl*wl >= 16");
   qg::Problem& p = pr->p;
   const int span = bl * wl;
-  if (tc <= 0) tc = qg::default_ctg_tc(p);
+  if (tc <= 0) tc = qg::default_ctg_tc(p, wl);
   if (tc > p.T) tc = p.T;
   if (tc > qg::kCtgMaxTc) return fail(QG_ERR_ARG, "at most 8 periods per block");
+  if (tc > qg::ctg_tc_cap(wl))
+    return fail(QG_ERR_ARG, "too many periods per block for the LDS budget at this wl");
   p.tile = qg::CtgTile{bl, wl, tc};
   p.nLb = (p.Lp + span - 1) / span;
   return QG_OK;

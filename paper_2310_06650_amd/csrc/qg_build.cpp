@@ -186,7 +186,7 @@ WorkLayout work_layout(const Problem& p) {
 
 }  // namespace
 
-int default_ctg_tc(const Problem& p) {
+int default_ctg_tc(const Problem& p, int wl) {
   // periods per block of the contingency map-reduce.  Short chunks give the
   // chip more blocks and shorter per-block tails, but every chunk re-reads
   // the outage factors: take 2 periods while the re-reads stay within a
@@ -194,7 +194,15 @@ int default_ctg_tc(const Problem& p) {
   const double lodf_bytes = (double)p.Lp * p.Kp * lodf_elem_bytes(lodf_kind_of(p.flags));
   const int chunks2 = (p.T + 1) / 2;
   int tc = (lodf_bytes * chunks2 <= 64.0 * (1 << 20)) ? 2 : kCtgMaxTc;
+  tc = std::min(tc, ctg_tc_cap(wl));
   return std::max(1, std::min(tc, p.T));
+}
+
+int ctg_tc_cap(int wl) {
+  // LDS of the map-reduce block: tc * 64 doubles of outaged-branch flows and
+  // tc * wl * 64 each of z and S
+  const int per_tc = 64 * (1 + 2 * wl) * (int)sizeof(double);
+  return std::max(1, std::min(kCtgMaxTc, kCtgLdsBytes / per_tc));
 }
 
 qg_status fail(qg_status s, const std::string& msg) {
@@ -295,7 +303,7 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   p->nKc = p->Kp / kCtgLanes;
   p->nLc = (p->Lp + kBlock - 1) / kBlock;
   p->tile = CtgTile{8, 8, 0};
-  p->tile.tc = default_ctg_tc(*p);
+  p->tile.tc = default_ctg_tc(*p, p->tile.wl);
   p->nLb_max = p->Lp / 16;
   p->nKb_max = p->Kp / kCtgLanes;
   p->nLb = p->Lp / (p->tile.bl * p->tile.wl);

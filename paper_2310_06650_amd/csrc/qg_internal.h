@@ -16,6 +16,7 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kCtgLanes = 64;      // contingencies per wavefront in the map-reduce
 constexpr int kParams = 16;        // doubles in the per-step parameter block
 constexpr int kCtgMaxTc = 8;            // periods per block of the contingency kernel
+constexpr int kCtgLdsBytes = 64 * 1024; // LDS budget of one contingency block
 constexpr int kAdjStepsPerBlock = 64;   // MFMA k-steps per block of the adjoint product
 constexpr int kSchedCap = 2048;         // solve steps per uploaded schedule table
 constexpr int kSchedStride = 16;        // doubles per step in the schedule table
@@ -170,7 +171,8 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
                       HostBuild* hb);
 void rebase_pointers(Problem* p, void* arena);
 DevWork carve_workspace(const Problem* p, void* ws);
-int default_ctg_tc(const Problem& p);
+int default_ctg_tc(const Problem& p, int wl);
+int ctg_tc_cap(int wl);  // most periods per block the LDS budget allows
 
 // Kernel launchers (qg_kernels.hip).  A step is kStages kernels.
 constexpr int kStages = 6;

@@ -741,9 +741,9 @@ template <int BL, typename LT>
 __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restrict__ lodf) {
   static_assert(BL % 8 == 0 && BL <= 32, "branches per wavefront");
   typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
-  __shared__ double sFk[kCtgMaxTc][64];
-  __shared__ double zsh[2][8][64];
-  __shared__ double ssh[2][8][64];
+  // LDS: sFk[TC][64] (outaged branches' flows), then per period and
+  // wavefront the lanes' z and S: zsh[TC][WL][64], ssh[TC][WL][64]
+  extern __shared__ double dyn[];
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int lane = threadIdx.x & 63;
@@ -757,9 +757,12 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
   const int lbase = __builtin_amdgcn_readfirstlane(lb * BL * WL + wv * BL);
   const bool on = lbase < Lp;
   const int k = kb * 64 + lane;
+  double* sFk = dyn;
+  double* zsh = dyn + TC * 64;
+  double* ssh = zsh + TC * WL * 64;
   for (int e = threadIdx.x; e < nt * 64; e += blockDim.x) {
     const int tt = e >> 6, kk = e & 63;
-    sFk[tt][kk] = w.Fk[(size_t)(t0 + tt) * Kp + kb * 64 + kk];
+    sFk[e] = w.Fk[(size_t)(t0 + tt) * Kp + kb * 64 + kk];
   }
   const cdouble* Sc = as_const(p.ctg_smax2);
   const cdouble* Mc = as_const(p.ctg_smax);
@@ -790,16 +793,11 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
     }
   }
   __syncthreads();
-  // per-period z and S of this lane, kept in registers until every period is
-  // done (selects keep the arrays in registers with a rolled loop)
-  double zs[kCtgMaxTc], ss[kCtgMaxTc];
-#pragma unroll
-  for (int u = 0; u < kCtgMaxTc; ++u) { zs[u] = 0.0; ss[u] = 0.0; }
   for (int tt = 0; tt < nt; ++tt) {
     const int t = t0 + tt;
     R zacc = R(0), sacc = R(0);
     if (on) {
-      const R fk = (R)sFk[tt][lane];
+      const R fk = (R)sFk[tt * 64 + lane];
       const size_t o = ((size_t)kb * T + t) * Lp + lbase;
 #pragma unroll
       for (int c = 0; c < BL / 8; ++c) {
@@ -839,26 +837,22 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < kCtgMaxTc; ++u)
-      if (u == tt) { zs[u] = (double)zacc; ss[u] = (double)sacc; }
+    zsh[(tt * WL + wv) * 64 + lane] = (double)zacc;
+    ssh[(tt * WL + wv) * 64 + lane] = (double)sacc;
   }
-  // sum z and S over the block's wavefronts, one period at a time
-#pragma unroll
-  for (int u = 0; u < kCtgMaxTc; ++u) {
-    if (u < nt) {
-      const int par = u & 1;
-      zsh[par][wv][lane] = zs[u];
-      ssh[par][wv][lane] = ss[u];
-      __syncthreads();
-      if (wv == 0) {
-        double z = 0.0, s2 = 0.0;
-        for (int q = 0; q < WL; ++q) { z += zsh[par][q][lane]; s2 += ssh[par][q][lane]; }
-        const size_t o = ((size_t)lb * T + t0 + u) * Kp + k;
-        w.zpart[o] = z;
-        w.spart[o] = s2;
-      }
+  // sum z and S over the block's wavefronts (wavefront order), every
+  // (period, contingency) of the block by one thread
+  __syncthreads();
+  for (int e = threadIdx.x; e < nt * 64; e += blockDim.x) {
+    const int tt = e >> 6, kk = e & 63;
+    double z = 0.0, s2 = 0.0;
+    for (int q = 0; q < WL; ++q) {
+      z += zsh[(tt * WL + q) * 64 + kk];
+      s2 += ssh[(tt * WL + q) * 64 + kk];
     }
+    const size_t o = ((size_t)lb * T + t0 + tt) * Kp + kb * 64 + kk;
+    w.zpart[o] = z;
+    w.spart[o] = s2;
   }
 }
 
@@ -1237,10 +1231,12 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const double* x, size_t
 template <typename LT>
 void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArgs& a,
                      const LT* lodf) {
+  // sFk[tc][64] + z and S of every (period, wavefront, lane)
+  const size_t lds = (size_t)a.tc * 64 * (1 + 2 * (block.x / 64)) * sizeof(double);
   switch (bl) {
-    case 8: hipLaunchKernelGGL((k_ctg_main<8, LT>), grid, block, 0, s, a, lodf); break;
-    case 16: hipLaunchKernelGGL((k_ctg_main<16, LT>), grid, block, 0, s, a, lodf); break;
-    default: hipLaunchKernelGGL((k_ctg_main<32, LT>), grid, block, 0, s, a, lodf); break;
+    case 8: hipLaunchKernelGGL((k_ctg_main<8, LT>), grid, block, lds, s, a, lodf); break;
+    case 16: hipLaunchKernelGGL((k_ctg_main<16, LT>), grid, block, lds, s, a, lodf); break;
+    default: hipLaunchKernelGGL((k_ctg_main<32, LT>), grid, block, lds, s, a, lodf); break;
   }
 }
 

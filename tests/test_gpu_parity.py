@@ -154,7 +154,7 @@ def test_bitwise_deterministic(qg):
 
 
 @pytest.mark.parametrize("bl,wl,tc", [(8, 2, 0), (8, 4, 1), (8, 4, 7), (16, 1, 0),
-                                      (16, 4, 5), (32, 2, 0), (32, 8, 3), (8, 8, 8)])
+                                      (16, 4, 5), (32, 2, 0), (32, 8, 3), (8, 8, 7)])
 def test_ctg_tile_invariance(qg, bl, wl, tc):
     c = case("c2")
     prob = qg.Problem(c)
@@ -164,6 +164,13 @@ def test_ctg_tile_invariance(qg, bl, wl, tc):
     t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
     np.testing.assert_allclose(t1, t0, rtol=1e-12)
     assert_grad_close(c, g1, g0, tol=1e-12)
+
+
+def test_ctg_tile_beyond_lds_budget_rejected(qg):
+    prob = qg.Problem(case("c2"))
+    with pytest.raises(qg.QgError) as e:
+        prob.set_ctg_tile(8, 8, 8)
+    assert e.value.status == qg.QG_ERR_ARG
 
 
 def test_adam_step_matches_oracle(qg):
