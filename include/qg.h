@@ -203,6 +203,18 @@ qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
                            qg_problem** out);
 
 /* Offsets and lengths of the six blocks of x. */
+/*
+ * New loads on the same grid (warm-start workflows: the topology, the factor
+ * and the outage factors are kept): load_p, load_q [T*N] period-major and
+ * reserve_req [T], host arrays read during the call.  Re-derives the
+ * load-dependent constants (total load, the flow constant ISF load - rowsum
+ * total / N, the consumer value), uploads them into the constant arena on the
+ * stream and synchronises it; a step graph cached by qg_solve is dropped.
+ * Errors: ARG (null or non-finite input), DEVICE.
+ */
+qg_status qg_update_loads(qg_problem* prob, const double* load_p, const double* load_q,
+                          const double* reserve_req, void* stream);
+
 qg_status qg_layout_of(const qg_problem* prob, qg_layout* out);
 
 /* Copy the contingency list actually used (K entries) into host memory. */

@@ -101,6 +101,44 @@ qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
   return QG_OK;
 }
 
+qg_status qg_update_loads(qg_problem* pr, const double* load_p, const double* load_q,
+                          const double* reserve_req, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!load_p || !load_q || !reserve_req) return fail(QG_ERR_ARG, "null load array");
+  qg::Problem& p = pr->p;
+  const size_t TN = (size_t)p.T * p.N;
+  for (size_t e = 0; e < TN; ++e)
+    if (!std::isfinite(load_p[e]) || !std::isfinite(load_q[e]))
+      return fail(QG_ERR_ARG, "non-finite load");
+  for (int t = 0; t < p.T; ++t)
+    if (!std::isfinite(reserve_req[t])) return fail(QG_ERR_ARG, "non-finite reserve requirement");
+  qg::LoadBlock lb;
+  qg::load_block(&p, load_p, &lb);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* base = static_cast<unsigned char*>(p.arena);
+  // the stream's earlier work may still read the old values
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  HIP_TRY(hipMemcpyAsync(base + lb.off_lp, load_p, TN * sizeof(double), hipMemcpyHostToDevice,
+                         st), "load upload");
+  HIP_TRY(hipMemcpyAsync(base + lb.off_lq, load_q, TN * sizeof(double), hipMemcpyHostToDevice,
+                         st), "load upload");
+  HIP_TRY(hipMemcpyAsync(base + lb.off_rsv, reserve_req, p.T * sizeof(double),
+                         hipMemcpyHostToDevice, st), "load upload");
+  HIP_TRY(hipMemcpyAsync(base + lb.off_sum, lb.sum_load.data(), p.T * sizeof(double),
+                         hipMemcpyHostToDevice, st), "load upload");
+  HIP_TRY(hipMemcpyAsync(base + lb.off_cload, lb.cload.data(), lb.cload.size() * sizeof(double),
+                         hipMemcpyHostToDevice, st), "load upload");
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  p.dp.vload = lb.vload;
+  // a cached step graph holds the old consumer value among its arguments
+  if (p.graph_exec) {
+    (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p.graph_exec));
+    p.graph_exec = nullptr;
+  }
+  return QG_OK;
+}
+
 qg_status qg_layout_of(const qg_problem* pr, qg_layout* out) {
   qg_status s = check_problem(pr);
   if (s != QG_OK) return s;

@@ -552,18 +552,9 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
         ga[(size_t)l * G16 + j] = v - rsum[l] / (double)N;
       }
     }
-    double* cl_ = reinterpret_cast<double*>(img.data() + cl.off[44]);  // [T][Lp]
-    parallel_for(T, [&](int t) {
-      const double* ld = d->load_p + (size_t)t * N;
-      for (int l = 0; l < L; ++l) {
-        const double* row = &isf[(size_t)l * Np];
-        double s = 0.0;
-        for (int i = 0; i < N; ++i) s += row[i] * ld[i];
-        cl_[(size_t)t * Lp + l] = s - rsum[l] * sum_load[t] / (double)N;
-      }
-    });
     put(img, cl.off[45], rsum.data(), Lp);
     (void)G4;
+    p->rsum_host = rsum;
   }
 
   // ---- outage factors, NaN on the outaged branch itself and on padding
@@ -606,6 +597,17 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
     }
   }
 
+  // ---- host data for load updates, and the load-dependent flow constant
+  p->isf_host = std::move(isf);
+  p->isf_np = Np;
+  p->dt_host.assign(d->dt, d->dt + T);
+  p->load_value = d->load_value;
+  {
+    LoadBlock lb;
+    load_block(p, d->load_p, &lb);
+    put(img, lb.off_cload, lb.cload.data(), (size_t)T * Lp);
+  }
+
   // ---- scalars
   DevProblem& dp = p->dp;
   dp.N = N; dp.L = L; dp.G = G; dp.T = T; dp.M = M; dp.K = K;
@@ -613,6 +615,35 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
   dp.c_p = d->c_p; dp.c_q = d->c_q; dp.c_s = d->c_s; dp.c_ang = d->c_ang;
   dp.ang_max = d->ang_max; dp.c_rsv = d->c_rsv; dp.rho = d->rho; dp.vload = vload;
   return QG_OK;
+}
+
+void load_block(const Problem* p, const double* load_p, LoadBlock* out) {
+  const ConstLayout cl = const_layout(*p);
+  const int N = p->N, L = p->L, T = p->T, Lp = p->Lp, Np = p->isf_np;
+  out->off_lp = cl.off[36];
+  out->off_lq = cl.off[37];
+  out->off_rsv = cl.off[39];
+  out->off_sum = cl.off[40];
+  out->off_cload = cl.off[44];
+  out->sum_load.assign(T, 0.0);
+  out->vload = 0.0;
+  for (int t = 0; t < T; ++t) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += load_p[(size_t)t * N + i];
+    out->sum_load[t] = s;
+    out->vload += p->dt_host[t] * p->load_value * s;
+  }
+  out->cload.assign((size_t)T * Lp, 0.0);
+  const double* isf = p->isf_host.data();
+  parallel_for(T, [&](int t) {
+    const double* ld = load_p + (size_t)t * N;
+    for (int l = 0; l < L; ++l) {
+      const double* row = &isf[(size_t)l * Np];
+      double s = 0.0;
+      for (int i = 0; i < N; ++i) s += row[i] * ld[i];
+      out->cload[(size_t)t * Lp + l] = s - p->rsum_host[l] * out->sum_load[t] / (double)N;
+    }
+  });
 }
 
 void rebase_pointers(Problem* p, void* arena) {

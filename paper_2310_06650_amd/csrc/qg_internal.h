@@ -153,6 +153,12 @@ struct Problem {
   int graph_steps = 0;
   EvalMode graph_mode{};
   CtgTile graph_tile{};   // contingency tile the cached graph was captured with
+  // host data kept for load updates (same grid, new loads)
+  std::vector<double> isf_host;  // [L][isf_np] injection shift factors (reference column 0)
+  int isf_np = 0;
+  std::vector<double> rsum_host; // [Lp] ISF row sums
+  std::vector<double> dt_host;   // [T]
+  double load_value = 0.0;
 };
 
 // Host build products (before upload).
@@ -170,6 +176,15 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
 qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
                       HostBuild* hb);
 void rebase_pointers(Problem* p, void* arena);
+// Load-dependent parts of the arena for new loads: byte offsets and host
+// values of load_p, load_q, rsv_req, sum_load and the flow constant, and the
+// consumer value.  Uses the ISF kept at build.
+struct LoadBlock {
+  size_t off_lp, off_lq, off_rsv, off_sum, off_cload;
+  std::vector<double> sum_load, cload;
+  double vload;
+};
+void load_block(const Problem* p, const double* load_p, LoadBlock* out);
 DevWork carve_workspace(const Problem* p, void* ws);
 int default_ctg_tc(const Problem& p, int wl);
 int ctg_tc_cap(int wl);  // most periods per block the LDS budget allows

@@ -117,6 +117,7 @@ _sig = {
     "qg_layout_of": (C.c_int, [_vp, C.POINTER(qg_layout)]),
     "qg_ctg_list": (C.c_int, [_vp, _pi, C.c_int32]),
     "qg_problem_dims": (C.c_int, [_vp, _pi, C.c_int32]),
+    "qg_update_loads": (C.c_int, [_vp, _pd, _pd, _pd, _vp]),
     "qg_time_stage": (C.c_int, [_vp, _vp, C.POINTER(qg_homotopy), C.c_int32, C.c_int32, _vp,
                                 _vp, C.POINTER(C.c_double)]),
     "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
@@ -339,6 +340,17 @@ class Problem:
         if host is not None:
             t.copy_(self.torch.as_tensor(np.asarray(host, dtype=np.float64)))
         return t
+
+    def update_loads(self, load_p, load_q, reserve_req):
+        """Same grid, new loads (arrays [T, N], [T, N], [T])."""
+        lp = np.ascontiguousarray(load_p, dtype=np.float64).reshape(-1)
+        lq = np.ascontiguousarray(load_q, dtype=np.float64).reshape(-1)
+        rr = np.ascontiguousarray(reserve_req, dtype=np.float64).reshape(-1)
+        if lp.size != self.dims["T"] * self.dims["N"] or lq.size != lp.size or \
+                rr.size != self.dims["T"]:
+            raise ValueError("load arrays do not match the grid")
+        _check(lib.qg_update_loads(self.handle, lp.ctypes.data_as(_pd), lq.ctypes.data_as(_pd),
+                                   rr.ctypes.data_as(_pd), self._stream()), "qg_update_loads")
 
     def time_stage(self, x, stage, reps, eps, beta=1.0, rho_scale=1.0):
         """Mean microseconds of one kernel of the step (index into KERNEL_NAMES)."""

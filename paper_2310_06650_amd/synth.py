@@ -36,7 +36,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["GridCase", "make_case", "CONFIGS", "config_case", "flat_start",
+__all__ = ["GridCase", "make_case", "CONFIGS", "config_case", "load_draw", "with_loads",
+           "flat_start",
            "random_point"]
 
 
@@ -366,6 +367,38 @@ def config_case(name: str, **overrides) -> GridCase:
     kw = dict(CONFIGS[name])
     kw.update(overrides)
     return make_case(name=name, **kw)
+
+
+def load_draw(case: GridCase, seed: int, phase_hours: float = 2.0,
+              level: tuple = (0.85, 1.0)):
+    """Loads of one operating day on the same grid: bus weights lognormal(0,
+    0.3) drawn afresh, the daily profile shifted by U[-phase_hours,
+    +phase_hours] hours, and the peak total scaled to U[level] times the
+    grid's own peak.  Power factors as in the grid.  Returns (load_p, load_q,
+    reserve_req) shaped [T, N], [T, N], [T]."""
+    rng = np.random.default_rng(seed)
+    T, N = case.n_period, case.n_bus
+    dt = case.dt[0]
+    shift = rng.uniform(-phase_hours, phase_hours)
+    hours = np.arange(T) * dt
+    profile = 1.0 + 0.2 * np.sin(2.0 * math.pi * (hours - 9.0 - shift) / 24.0)
+    mu = rng.lognormal(0.0, 0.3, size=N)
+    raw = profile[:, None] * mu[None, :]
+    peak = case.load_p.sum(axis=1).max() * rng.uniform(*level)
+    load_p = raw * (peak / raw.sum(axis=1).max())
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(case.load_p > 0, case.load_q / case.load_p, 0.0)
+    load_q = load_p * ratio[0][None, :]
+    reserve_req = 0.1 * load_p.sum(axis=1)
+    return load_p, load_q, reserve_req
+
+
+def with_loads(case: GridCase, draw) -> GridCase:
+    """The same grid with the loads of a draw (see load_draw)."""
+    load_p, load_q, reserve_req = draw
+    return dataclasses.replace(case, load_p=np.asarray(load_p, dtype=np.float64),
+                               load_q=np.asarray(load_q, dtype=np.float64),
+                               reserve_req=np.asarray(reserve_req, dtype=np.float64))
 
 
 def flat_start(case: GridCase, dispatch: Optional[np.ndarray] = None) -> np.ndarray:

@@ -122,3 +122,19 @@ def test_precision_flags_size_the_factor_storage():
     assert e.value.status == qg.QG_ERR_ARG
     with pytest.raises(qg.QgError):
         _sizes(c, flags=0x100)
+
+
+def test_load_draws_keep_the_grid():
+    c = synth.config_case("c2")
+    a = synth.load_draw(c, 10000)
+    b = synth.load_draw(c, 10000)
+    d = synth.load_draw(c, 10001)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
+    assert not np.array_equal(a[0], d[0])
+    lp, lq, rr = a
+    assert lp.shape == c.load_p.shape and (lp > 0).all()
+    peak = lp.sum(axis=1).max() / c.load_p.sum(axis=1).max()
+    assert 0.85 - 1e-12 <= peak <= 1.0 + 1e-12
+    assert np.allclose(rr, 0.1 * lp.sum(axis=1))
+    c2 = synth.with_loads(c, a)
+    assert c2.n_bus == c.n_bus and np.array_equal(c2.br_x, c.br_x)

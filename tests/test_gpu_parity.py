@@ -344,3 +344,36 @@ def test_time_stage_leaves_results_unchanged(qg):
     assert np.array_equal(t1, t2) and np.array_equal(g1, g2)
     with pytest.raises(qg.QgError):
         prob.time_stage(xd, 6, 5, 1e-2)
+
+
+def test_update_loads_matches_fresh_build(qg):
+    """New loads on a built problem give the problem built with those loads,
+    bit for bit, for evaluations and for graph-replayed solves (a graph
+    captured before the update is not reused)."""
+    import torch
+    c = case("c2")
+    draw = synth.load_draw(c, 10001)
+    c2 = synth.with_loads(c, draw)
+    fresh = qg.Problem(c2)
+    upd = qg.Problem(c)
+    x0 = synth.flat_start(c)
+    opts = dict(alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3)
+    xd, md, vd = upd.new_vector(x0), upd.new_vector(), upd.new_vector()
+    upd.solve(xd, md, vd, qg.solve_opts(8, [1e-3] * 6, use_graph=1, **opts))
+    upd.update_loads(*draw)
+    x = synth.random_point(c2, 21, spread=0.3)
+    t1, g1 = gpu_eval(qg, fresh, x, 1e-2, 1.0, 1.0)
+    t2, g2 = gpu_eval(qg, upd, x, 1e-2, 1.0, 1.0)
+    assert np.array_equal(t1, t2) and np.array_equal(g1, g2)
+    tr, gr = ob.evaluate(oracle_model(c2), x, 1e-2, 1.0, 1.0)
+    assert_terms_close(qg, t2, tr)
+    assert_grad_close(c2, g2, gr)
+    outs = []
+    for prob in (fresh, upd):
+        xd.copy_(torch.from_numpy(x0).to(xd.device))
+        md.zero_()
+        vd.zero_()
+        prob.solve(xd, md, vd, qg.solve_opts(8, [1e-3] * 6, use_graph=1, **opts))
+        torch.cuda.synchronize()
+        outs.append(xd.cpu().numpy().copy())
+    assert np.array_equal(outs[0], outs[1])
