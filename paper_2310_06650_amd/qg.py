@@ -108,6 +108,19 @@ class qg_solve_report(C.Structure):
                 ("kernel_calls", C.c_int64 * QG_NKERNELS)]
 
 
+QG_MLP_MAX_DEPTH = 8
+
+
+class qg_mlp_desc(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
+                ("d_out", C.c_int32)]
+
+
+class qg_mlp_layout(C.Structure):
+    _fields_ = [("n_params", C.c_int64), ("w_off", C.c_int64 * (QG_MLP_MAX_DEPTH + 1)),
+                ("b_off", C.c_int64 * (QG_MLP_MAX_DEPTH + 1))]
+
+
 _vp = C.c_void_p
 _sig = {
     "qg_problem_sizes": (C.c_int, [C.POINTER(qg_grid_desc), C.POINTER(qg_build_opts),
@@ -128,6 +141,16 @@ _sig = {
                            C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp, _vp]),
     "qg_debug_fetch": (C.c_int, [_vp, _vp, C.c_char_p, _vp, C.c_size_t, _vp]),
     "qg_destroy_problem": (None, [_vp]),
+    "qg_mlp_sizes": (C.c_int, [C.POINTER(qg_mlp_desc), C.c_int32, C.POINTER(qg_mlp_layout),
+                               C.POINTER(C.c_size_t)]),
+    "qg_mlp_forward": (C.c_int, [C.POINTER(qg_mlp_desc), _vp, _vp, C.c_int32, _vp, _vp, _vp]),
+    "qg_mlp_grad": (C.c_int, [C.POINTER(qg_mlp_desc), _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp,
+                              _vp]),
+    "qg_mlp_train_step": (C.c_int, [C.POINTER(qg_mlp_desc), _vp, _vp, _vp, _vp, _vp, _vp,
+                                    C.c_int32, C.c_int64, C.c_float, _vp, _vp, _vp]),
+    "qg_mlp_to_bf16": (C.c_int, [C.POINTER(qg_mlp_desc), _vp, _vp, _vp]),
+    "qg_mlp_forward_bf16": (C.c_int, [C.POINTER(qg_mlp_desc), _vp, _vp, C.c_int32, _vp, _vp,
+                                      _vp]),
     "qg_status_string": (C.c_char_p, [C.c_int]),
     "qg_last_error": (C.c_char_p, []),
 }
@@ -402,3 +425,95 @@ def report_dict(rep):
                 terms=dict(zip(TERM_NAMES, list(rep.terms))),
                 kernel_ms=dict(zip(KERNEL_NAMES, list(rep.kernel_ms)[:len(KERNEL_NAMES)])),
                 kernel_calls=dict(zip(KERNEL_NAMES, list(rep.kernel_calls)[:len(KERNEL_NAMES)])))
+
+
+class MLP:
+    """Device buffers of the warm-start network (FP32 parameters, Adam moments,
+    gradient scratch and workspace) on a GPU, driven through the qg_mlp ABI."""
+
+    def __init__(self, d_in, width, depth, d_out, max_batch, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.desc = qg_mlp_desc(d_in, width, depth, d_out)
+        self.layout = qg_mlp_layout()
+        ws = C.c_size_t(0)
+        _check(lib.qg_mlp_sizes(C.byref(self.desc), int(max_batch), C.byref(self.layout),
+                                C.byref(ws)), "qg_mlp_sizes")
+        self.max_batch = int(max_batch)
+        self.n_params = int(self.layout.n_params)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.params = torch.zeros(self.n_params, **f32)
+        self.m = torch.zeros(self.n_params, **f32)
+        self.v = torch.zeros(self.n_params, **f32)
+        self.grad = torch.zeros(self.n_params, **f32)
+        self.loss = torch.zeros(64, **f32)
+        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=self.device)
+        self.params16 = None
+        self.stream = stream
+        self.iter = 0
+
+    def _stream(self):
+        s = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def offsets(self, i):
+        """(weight offset, bias offset) of layer i (0-based; depth = output layer)."""
+        return int(self.layout.w_off[i]), int(self.layout.b_off[i])
+
+    def set_params(self, host):
+        self.params.copy_(self.torch.as_tensor(np.asarray(host, dtype=np.float32)))
+        self.m.zero_()
+        self.v.zero_()
+        self.iter = 0
+
+    def _ws(self):
+        p = self.workspace.data_ptr()
+        return C.c_void_p((p + 255) // 256 * 256)
+
+    def forward(self, x, out=None):
+        b = int(x.shape[0])
+        if b > self.max_batch:
+            raise ValueError("batch larger than the workspace")
+        out = out if out is not None else self.torch.empty((b, self.desc.d_out),
+                                                           dtype=self.torch.float32,
+                                                           device=self.device)
+        _check(lib.qg_mlp_forward(C.byref(self.desc), self.params.data_ptr(), x.data_ptr(), b,
+                                  out.data_ptr(), self._ws(), self._stream()), "qg_mlp_forward")
+        return out
+
+    def grad_and_loss(self, x, t):
+        b = int(x.shape[0])
+        _check(lib.qg_mlp_grad(C.byref(self.desc), self.params.data_ptr(), x.data_ptr(),
+                               t.data_ptr(), b, self.grad.data_ptr(), self.loss.data_ptr(),
+                               self._ws(), self._stream()), "qg_mlp_grad")
+        return self.grad, self.loss[0]
+
+    def train_step(self, x, t, lr):
+        b = int(x.shape[0])
+        self.iter += 1
+        _check(lib.qg_mlp_train_step(C.byref(self.desc), self.params.data_ptr(),
+                                     self.m.data_ptr(), self.v.data_ptr(), self.grad.data_ptr(),
+                                     x.data_ptr(), t.data_ptr(), b, self.iter, float(lr),
+                                     self.loss.data_ptr(), self._ws(), self._stream()),
+               "qg_mlp_train_step")
+        return self.loss[0]
+
+    def to_bf16(self):
+        if self.params16 is None:
+            self.params16 = self.torch.empty(self.n_params, dtype=self.torch.int16,
+                                             device=self.device)
+        _check(lib.qg_mlp_to_bf16(C.byref(self.desc), self.params.data_ptr(),
+                                  self.params16.data_ptr(), self._stream()), "qg_mlp_to_bf16")
+
+    def forward_bf16(self, x, out=None):
+        b = int(x.shape[0])
+        if self.params16 is None:
+            self.to_bf16()
+        out = out if out is not None else self.torch.empty((b, self.desc.d_out),
+                                                           dtype=self.torch.float32,
+                                                           device=self.device)
+        _check(lib.qg_mlp_forward_bf16(C.byref(self.desc), self.params16.data_ptr(),
+                                       x.data_ptr(), b, out.data_ptr(), self._ws(),
+                                       self._stream()), "qg_mlp_forward_bf16")
+        return out

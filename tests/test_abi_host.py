@@ -17,8 +17,11 @@ qg = pytest.importorskip("paper_2310_06650_amd.qg",
 
 
 def _declared_symbols():
-    with open(os.path.join(ROOT, "include", "qg.h")) as f:
-        text = f.read()
+    text = ""
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            with open(os.path.join(ROOT, "include", name)) as f:
+                text += f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(qg_[a-z_]+)\s*\(", text)))
 
