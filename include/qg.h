@@ -262,6 +262,23 @@ qg_status qg_solve(qg_problem* prob, double* d_x, double* d_m, double* d_v,
                    qg_solve_report* report, void* d_workspace, void* stream);
 
 /*
+ * Batched solve of independent scenarios (problems built separately, of any
+ * sizes): the same schedule and Adam constants for all, n_steps steps each,
+ * in one HIP graph per 16 steps in which every scenario's steps form their
+ * own branch, so that small scenarios run side by side on the GPU.  Arrays of
+ * n entries (n <= QG_BATCH_MAX): problems, x, m, v, workspaces (caller-owned,
+ * as for qg_solve) and reports.  No gap checks or profiling (check_every and
+ * profile must be 0).  reports[i].wall_s is the batch's wall time of the
+ * steps (graph capture excluded).  Synchronises the stream.
+ * Errors: ARG, DEVICE.
+ */
+#define QG_BATCH_MAX 256
+qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x,
+                         double* const* d_m, double* const* d_v, void* const* d_workspace,
+                         const qg_solve_opts* opts, const qg_adam_cfg* cfg,
+                         qg_solve_report* reports, void* stream);
+
+/*
  * Padded sizes and launch geometry, for tests and tools: dims[0..15] =
  * N, L, G, T, M, K, Lp, Kp, G16, G4, Tp, nLb, nKb, ctg_bl, ctg_wl, ctg_tc
  * (Lp = L rounded up to 64, Kp = K up to 64, G16 = G up to 16, G4 = G up to 4,

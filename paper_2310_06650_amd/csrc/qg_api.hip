@@ -268,17 +268,30 @@ qg_status qg_adam_step(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   return QG_OK;
 }
 
-qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
-                   const qg_solve_opts* o, const qg_adam_cfg* cfg, qg_solve_report* rep,
-                   void* d_workspace, void* stream) {
-  using clock = std::chrono::steady_clock;
-  const auto t_start = clock::now();
-  qg_status s = check_problem(pr);
-  if (s != QG_OK) return s;
-  if (!d_x || !d_m || !d_v || !o || !cfg || !rep || !d_workspace)
-    return fail(QG_ERR_ARG, "null argument");
-  if (!aligned(d_x) || !aligned(d_m) || !aligned(d_v) || !aligned(d_workspace))
-    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+// Rows of the per-step schedule table for steps first .. first+count-1:
+// eqs. (norm_t)-(step_size) indexed by the iteration i (t0 = 0, tf = n_total)
+// for eps and the step sizes, linear ramps for beta and rho, and the Adam
+// bias corrections.
+static void fill_schedule(double* table, const qg_solve_opts* o, const qg_adam_cfg* cfg,
+                          int64_t n_total, int64_t first, int count) {
+  const double n = (double)n_total;
+  for (int q = 0; q < count; ++q) {
+    const double i = (double)(first + q);
+    const double th = 2.0 * i / n - 1.0;
+    const double e = std::exp(4.0 * th);
+    const double sc = e / (0.6 + e);
+    double* row = &table[(size_t)q * qg::kSchedStride];
+    row[0] = o->eps0 * std::pow(10.0, sc * std::log10(o->epsf / o->eps0));
+    row[1] = o->beta0 + (o->betaf - o->beta0) * (i / n);
+    row[2] = o->rho0 + (o->rhof - o->rho0) * (i / n);
+    for (int c = 0; c < QG_NCLASS; ++c)
+      row[3 + c] = o->alpha0[c] * std::pow(10.0, sc * std::log10(o->alphaf[c] / o->alpha0[c]));
+    row[9] = 1.0 - std::pow(cfg->beta1, i);
+    row[10] = 1.0 - std::pow(cfg->beta2, i);
+  }
+}
+
+static qg_status check_solve_opts(const qg_solve_opts* o, const qg_adam_cfg* cfg) {
   if (o->n_steps < 0 || o->iter0 < 0 || o->check_every < 0)
     return fail(QG_ERR_ARG, "negative step counts");
   const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
@@ -290,6 +303,23 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
       !(cfg->eps > 0.0))
     return fail(QG_ERR_ARG, "need 0 <= beta1, beta2 < 1 and eps > 0");
+  return QG_OK;
+}
+
+qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
+                   const qg_solve_opts* o, const qg_adam_cfg* cfg, qg_solve_report* rep,
+                   void* d_workspace, void* stream) {
+  using clock = std::chrono::steady_clock;
+  const auto t_start = clock::now();
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!d_x || !d_m || !d_v || !o || !cfg || !rep || !d_workspace)
+    return fail(QG_ERR_ARG, "null argument");
+  if (!aligned(d_x) || !aligned(d_m) || !aligned(d_v) || !aligned(d_workspace))
+    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+  s = check_solve_opts(o, cfg);
+  if (s != QG_OK) return s;
+  const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
 
   const qg::Problem& p = pr->p;
   qg::DevWork w = qg::carve_workspace(&p, d_workspace);
@@ -312,27 +342,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   sm.adam_b1 = cfg->beta1; sm.adam_b2 = cfg->beta2; sm.adam_eps = cfg->eps;
   sm.eps_in_num = cfg->eps_in_numerator;
 
-  // eqs. (norm_t)-(step_size) indexed by the iteration i (t0 = 0, tf = n_total)
   std::vector<double> table((size_t)qg::kSchedCap * qg::kSchedStride, 0.0);
-  auto fill = [&](int64_t first, int count) {
-    const double n = (double)n_total;
-    for (int q = 0; q < count; ++q) {
-      const double i = (double)(first + q);
-      const double th = 2.0 * i / n - 1.0;
-      const double e = std::exp(4.0 * th);
-      const double sc = e / (0.6 + e);
-      double* row = &table[(size_t)q * qg::kSchedStride];
-      row[0] = o->eps0 * std::pow(10.0, sc * std::log10(o->epsf / o->eps0));
-      row[1] = o->beta0 + (o->betaf - o->beta0) * (i / n);
-      row[2] = o->rho0 + (o->rhof - o->rho0) * (i / n);
-      for (int c = 0; c < QG_NCLASS; ++c)
-        row[3 + c] = o->alpha0[c] * std::pow(10.0, sc * std::log10(o->alphaf[c] / o->alpha0[c]));
-      row[9] = 1.0 - std::pow(cfg->beta1, i);
-      row[10] = 1.0 - std::pow(cfg->beta2, i);
-    }
-  };
   auto upload = [&](int64_t first, int count) -> qg_status {
-    fill(first, count);
+    fill_schedule(table.data(), o, cfg, n_total, first, count);
     HIP_TRY(hipMemcpyAsync(w.sched, table.data(), (size_t)count * qg::kSchedStride * sizeof(double),
                            hipMemcpyHostToDevice, ex), "schedule upload");
     if (qg::launch_set_step(&p, w, 0, ex) != 0) return hip_fail(hipGetLastError(), "launch");
@@ -476,6 +488,131 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     for (int q = 0; q < kKernels; ++q)
       if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
     for (auto& e : evs) (void)hipEventDestroy(e);
+  }
+  return QG_OK;
+}
+
+qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x,
+                         double* const* d_m, double* const* d_v, void* const* d_workspace,
+                         const qg_solve_opts* o, const qg_adam_cfg* cfg, qg_solve_report* reps,
+                         void* stream) {
+  using clock = std::chrono::steady_clock;
+  if (n < 1 || n > QG_BATCH_MAX || !probs || !d_x || !d_m || !d_v || !d_workspace || !o ||
+      !cfg || !reps)
+    return fail(QG_ERR_ARG, "bad batch arguments");
+  qg_status s = check_solve_opts(o, cfg);
+  if (s != QG_OK) return s;
+  if (o->check_every != 0 || o->profile != 0)
+    return fail(QG_ERR_ARG, "batched solves take no gap checks and no profiling");
+  for (int i = 0; i < n; ++i) {
+    s = check_problem(probs[i]);
+    if (s != QG_OK) return s;
+    if (!d_x[i] || !d_m[i] || !d_v[i] || !d_workspace[i] || !aligned(d_x[i]) ||
+        !aligned(d_m[i]) || !aligned(d_v[i]) || !aligned(d_workspace[i]))
+      return fail(QG_ERR_ARG, "null or misaligned buffer of scenario " + std::to_string(i));
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == probs[i]) return fail(QG_ERR_ARG, "a problem appears twice in the batch");
+  }
+  const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
+  std::vector<qg::DevWork> w(n);
+  for (int i = 0; i < n; ++i) w[i] = qg::carve_workspace(&probs[i]->p, d_workspace[i]);
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  hipStream_t ex = user ? user : probs[0]->own;
+
+  qg::EvalMode sm;
+  std::memset(&sm, 0, sizeof(sm));
+  sm.schedule = 1;
+  sm.adam_b1 = cfg->beta1; sm.adam_b2 = cfg->beta2; sm.adam_eps = cfg->eps;
+  sm.eps_in_num = cfg->eps_in_numerator;
+
+  // one graph of gsteps steps of every scenario: each scenario's steps on
+  // their own branch (its own stream during capture), joined at the end
+  const int gsteps = (int)std::min<int64_t>(16, std::max<int64_t>(1, o->n_steps));
+  hipGraphExec_t gexec = nullptr;
+  std::vector<hipEvent_t> evs(n + 1);
+  for (auto& e : evs) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  auto cleanup = [&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto& e : evs) (void)hipEventDestroy(e);
+  };
+  {
+    hipGraph_t g;
+    hipStream_t cap = probs[0]->own;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipEventRecord(evs[n], cap);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+      hipStream_t si = probs[i]->own;
+      if (i > 0) e = hipStreamWaitEvent(si, evs[n], 0);
+      for (int k = 0; k < gsteps && e == hipSuccess; ++k)
+        e = (hipError_t)qg::launch_eval(&probs[i]->p, w[i], d_x[i], nullptr, nullptr, sm, 1,
+                                        d_m[i], d_v[i], si, nullptr);
+      if (e == hipSuccess && i > 0) e = hipEventRecord(evs[i], si);
+      if (e == hipSuccess && i > 0) e = hipStreamWaitEvent(cap, evs[i], 0);
+    }
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) {
+      e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "batch graph capture"); }
+  }
+
+  const auto t_start = clock::now();
+  std::vector<double> table((size_t)qg::kSchedCap * qg::kSchedStride, 0.0);
+  int64_t done = 0;
+  while (done < o->n_steps) {
+    const int64_t nc = std::min<int64_t>(o->n_steps - done, qg::kSchedCap);
+    fill_schedule(table.data(), o, cfg, n_total, o->iter0 + done + 1, (int)nc);
+    for (int i = 0; i < n; ++i) {
+      hipError_t e = hipMemcpyAsync(w[i].sched, table.data(),
+                                    (size_t)nc * qg::kSchedStride * sizeof(double),
+                                    hipMemcpyHostToDevice, ex);
+      if (e == hipSuccess && qg::launch_set_step(&probs[i]->p, w[i], 0, ex) != 0)
+        e = hipGetLastError();
+      if (e != hipSuccess) { cleanup(); return hip_fail(e, "schedule upload"); }
+    }
+    int64_t left = nc;
+    for (; left >= gsteps; left -= gsteps) {
+      hipError_t e = hipGraphLaunch(gexec, ex);
+      if (e != hipSuccess) { cleanup(); return hip_fail(e, "graph launch"); }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int64_t k = 0; k < left; ++k)
+        if (qg::launch_eval(&probs[i]->p, w[i], d_x[i], nullptr, nullptr, sm, 1, d_m[i], d_v[i],
+                            ex, nullptr) != 0) {
+          cleanup();
+          return hip_fail(hipGetLastError(), "kernel launch");
+        }
+    done += nc;
+  }
+  hipError_t e = hipStreamSynchronize(ex);
+  if (e != hipSuccess) { cleanup(); return hip_fail(e, "sync"); }
+  const double wall = std::chrono::duration<double>(clock::now() - t_start).count();
+  cleanup();
+  // reports: the objective at the last schedule point and the score
+  for (int i = 0; i < n; ++i) {
+    qg_solve_report* r = &reps[i];
+    std::memset(r, 0, sizeof(*r));
+    r->steps_done = done;
+    r->steps_to_gap = -1;
+    r->time_to_gap_s = -1.0;
+    r->wall_s = wall;
+    double last[QG_NTERMS];
+    HIP_TRY(hipMemcpy(last, w[i].terms, sizeof(last), hipMemcpyDeviceToHost), "terms read");
+    r->final_loss = last[QG_T_TOTAL];
+    qg::EvalMode score{};
+    score.schedule = 0;
+    score.eps = 0.0;
+    score.beta = 1.0;
+    score.rho_s = o->rhof;
+    if (qg::launch_eval(&probs[i]->p, w[i], d_x[i], nullptr, nullptr, score, 0, nullptr, nullptr,
+                        ex, nullptr) != 0)
+      return hip_fail(hipGetLastError(), "kernel launch");
+    HIP_TRY(hipMemcpyAsync(r->terms, w[i].terms, QG_NTERMS * sizeof(double),
+                           hipMemcpyDeviceToHost, ex), "terms read");
+    HIP_TRY(hipStreamSynchronize(ex), "sync");
+    r->final_score = -r->terms[QG_T_TOTAL];
   }
   return QG_OK;
 }

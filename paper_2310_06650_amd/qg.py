@@ -140,6 +140,9 @@ _sig = {
     "qg_solve": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_solve_opts),
                            C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp, _vp]),
     "qg_debug_fetch": (C.c_int, [_vp, _vp, C.c_char_p, _vp, C.c_size_t, _vp]),
+    "qg_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                 C.POINTER(_vp), C.POINTER(_vp), C.POINTER(qg_solve_opts),
+                                 C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp]),
     "qg_destroy_problem": (None, [_vp]),
     "qg_mlp_sizes": (C.c_int, [C.POINTER(qg_mlp_desc), C.c_int32, C.POINTER(qg_mlp_layout),
                                C.POINTER(C.c_size_t)]),
@@ -517,3 +520,20 @@ class MLP:
                                        x.data_ptr(), b, out.data_ptr(), self._ws(),
                                        self._stream()), "qg_mlp_forward_bf16")
         return out
+
+
+def solve_batch(problems, xs, ms, vs, opts, cfg=None, stream=None):
+    """qg_solve_batch over Problem objects and their device vectors; returns
+    the per-scenario reports."""
+    import torch
+    n = len(problems)
+    arr = lambda vals: (_vp * n)(*[C.c_void_p(v) for v in vals])
+    reps = (qg_solve_report * n)()
+    cfg = cfg or adam_cfg()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.qg_solve_batch(arr([p.handle.value for p in problems]), n,
+                              arr([x.data_ptr() for x in xs]), arr([m.data_ptr() for m in ms]),
+                              arr([v.data_ptr() for v in vs]),
+                              arr([p.workspace.data_ptr() for p in problems]), C.byref(opts),
+                              C.byref(cfg), reps, C.c_void_p(st.cuda_stream)), "qg_solve_batch")
+    return list(reps)

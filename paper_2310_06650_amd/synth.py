@@ -36,7 +36,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["GridCase", "make_case", "CONFIGS", "config_case", "load_draw", "with_loads",
+__all__ = ["GridCase", "make_case", "CONFIGS", "config_case", "batch_cases", "load_draw",
+           "with_loads",
            "flat_start",
            "random_point"]
 
@@ -361,6 +362,21 @@ CONFIGS = {
     "c3": dict(seed=3, n_bus=2000, n_branch=2800, n_gen=300, n_period=48,
                n_ctg=2500, tree="prufer", mesh=3.0),
 }
+
+
+def batch_cases(n: int = 64, seed0: int = 4000, n_bus=(100, 2000), n_period=(12, 48)):
+    """Independent scenarios of uneven size for batched solves: bus counts and
+    period counts drawn uniformly from the given ranges, 1.4 branches and 0.15
+    generators per bus, every non-islanding outage, ratings as the configs."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(n):
+        N = int(rng.integers(n_bus[0], n_bus[1] + 1))
+        T = int(rng.integers(n_period[0], n_period[1] + 1))
+        out.append(make_case(seed=seed0 + 1 + i, n_bus=N, n_branch=int(round(1.4 * N)),
+                             n_gen=max(2, int(round(0.15 * N))), n_period=T, n_ctg=None,
+                             tree="prufer", mesh=3.0, name=f"batch-{i}"))
+    return out
 
 
 def config_case(name: str, **overrides) -> GridCase:

@@ -377,3 +377,47 @@ def test_update_loads_matches_fresh_build(qg):
         torch.cuda.synchronize()
         outs.append(xd.cpu().numpy().copy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_batched_solve_matches_single_solves(qg):
+    """Scenarios of different sizes solved together in one graph end where
+    each one solved alone ends, bit for bit."""
+    import torch
+    cases = synth.batch_cases(3, seed0=77, n_bus=(30, 120), n_period=(4, 12))
+    opts = qg.solve_opts(40, [1e-3] * 6, alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3, use_graph=1)
+    alone, probs, xs, ms, vs = [], [], [], [], []
+    for c in cases:
+        p = qg.Problem(c)
+        x0 = synth.flat_start(c)
+        x, m, v = p.new_vector(x0), p.new_vector(), p.new_vector()
+        p.solve(x, m, v, opts)
+        torch.cuda.synchronize()
+        alone.append(x.cpu().numpy().copy())
+        x.copy_(torch.from_numpy(x0).to(x.device))
+        m.zero_()
+        v.zero_()
+        probs.append(p)
+        xs.append(x)
+        ms.append(m)
+        vs.append(v)
+    reps = qg.solve_batch(probs, xs, ms, vs, opts)
+    torch.cuda.synchronize()
+    for a, x, r in zip(alone, xs, reps):
+        assert np.array_equal(a, x.cpu().numpy())
+        assert r.steps_done == 40 and np.isfinite(r.final_score)
+
+
+def test_autotuner_picks_a_timed_tile_and_caches_it(qg, tmp_path, monkeypatch):
+    from paper_2310_06650_amd import autotune
+    monkeypatch.setenv("QG_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    c = case("c2")
+    prob = qg.Problem(c)
+    x = prob.new_vector(synth.flat_start(c))
+    tile, times = autotune.tune(prob, x, reps=5)
+    assert times and f"{tile[0]}x{tile[1]}x{tile[2]}" in times
+    assert times[f"{tile[0]}x{tile[1]}x{tile[2]}"] == min(times.values())
+    d = prob.dims
+    assert (d["ctg_bl"], d["ctg_wl"], d["ctg_tc"]) == tile
+    prob2 = qg.Problem(c)
+    tile2, times2 = autotune.tune(prob2, prob2.new_vector(synth.flat_start(c)), reps=5)
+    assert tile2 == tile and times2 == times   # from the cache
