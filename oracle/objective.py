@@ -64,7 +64,7 @@ from . import network
 
 __all__ = ["TERMS", "Model", "make_model", "unpack", "branch_flows",
            "soft_relu", "soft_relu_grad", "soft_abs", "soft_abs_grad",
-           "evaluate", "ctg_term_bruteforce", "pwl_cost"]
+           "evaluate", "ctg_excess", "ctg_term_bruteforce", "pwl_cost"]
 
 TERMS = ("dev", "bal", "br", "ang", "pen", "rsv", "ctg_max", "ctg_mean",
          "load_value")
@@ -222,11 +222,22 @@ def qmax2(fl):
 # full evaluation
 # --------------------------------------------------------------------------
 
-def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None):
-    """Objective terms (dict) and, if asked, the gradient (flat, like x)."""
+def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None, active=None):
+    """Objective terms (dict) and, if asked, the gradient (flat, like x).
+
+    active: None (every contingency is scored) or the positions (into
+    model.ctg) of the contingencies scored this step, as in the contingency
+    solver of Alg. 2.  A contingency outside the set takes the penalty it has
+    with no overloaded branch, d_t c_s beta (L - 1) eps, a constant: it enters
+    the per-period max and mean with that value and backpropagates nothing.
+    """
     case = model.case
     T, N, G, L = case.n_period, case.n_bus, case.n_gen, case.n_branch
     K = model.ctg.shape[0]
+    act = np.ones(K, dtype=bool)
+    if active is not None:
+        act = np.zeros(K, dtype=bool)
+        act[np.asarray(active, dtype=np.int64)] = True
     V, TH, P, Q, R, U = unpack(case, np.asarray(x, dtype=np.float64))
     dt = case.dt
     terms = {}
@@ -323,6 +334,7 @@ def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None):
         sig = soft_relu(s - sctg[:, None], eps)
         sig[model.ctg, Kidx] = 0.0
         z[t] = kct[t] * sig.sum(axis=0)
+    z[:, ~act] = (kct * (L - 1) * eps)[:, None]
     kstar = np.argmax(z, axis=1) if K > 0 else np.zeros(T, dtype=np.int64)
     terms["ctg_max"] = float(z[np.arange(T), kstar].sum()) if K > 0 else 0.0
     terms["ctg_mean"] = float(z.mean(axis=1).sum()) if K > 0 else 0.0
@@ -340,8 +352,9 @@ def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None):
     Qc = np.zeros((T, L))       # dC/d qmax2
     if K > 0:
         for t in chunks:
-            w = np.full(K, 1.0 / K)
-            w[kstar[t]] += 1.0
+            w = np.where(act, 1.0 / K, 0.0)
+            if act[kstar[t]]:
+                w[kstar[t]] += 1.0
             Pk = F[t][:, None] + model.lodf * F[t, model.ctg][None, :]
             s = np.sqrt(Pk * Pk + q2[t][:, None])
             ds = soft_relu_grad(s - sctg[:, None], eps)
@@ -399,6 +412,28 @@ def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None):
 
     grad = pack(case, gV, gTH, gP, gQ, gR, gU)
     return terms, grad
+
+
+def ctg_excess(model, x, eps, beta):
+    """[T, K] penalty of each contingency above its no-overload value:
+    d_t c_s beta sum_{l != k} (sigma(s_tlk - s_ctg_l) - eps).  A branch that is
+    not overloaded adds exactly zero (sigma = eps there)."""
+    case = model.case
+    T = case.n_period
+    V, TH, P, Q, R, U = unpack(case, np.asarray(x, dtype=np.float64))
+    fl = branch_flows(model, V, TH)
+    q2, _ = qmax2(fl)
+    F = balanced_injection(case, P) @ model.isf.T
+    K = model.ctg.shape[0]
+    kct = case.dt * case.c_s * beta
+    out = np.zeros((T, K))
+    for t in range(T):
+        Pk = F[t][:, None] + model.lodf * F[t, model.ctg][None, :]
+        s = np.sqrt(Pk * Pk + q2[t][:, None])
+        ex = soft_relu(s - case.br_smax_ctg[:, None], eps) - eps
+        ex[model.ctg, np.arange(K)] = 0.0
+        out[t] = kct[t] * ex.sum(axis=0)
+    return out
 
 
 def ctg_term_bruteforce(model, x, eps, beta, return_z=False):
