@@ -251,7 +251,8 @@ qg_status qg_adam_step(qg_problem* prob, double* d_x, double* d_m, double* d_v,
 
 /*
  * Run n_steps of the Adam window of Alg. 4 (evaluate, backpropagate all
- * contingencies, Adam, clip) with iteration-indexed schedules: step sizes
+ * contingencies, or the screened set of qg_set_screening, Adam, clip) with
+ * iteration-indexed schedules: step sizes
  * per class and eps from eqs. (norm_t)-(step_size), beta and rho_scale
  * linear.  x, m, v are updated in place (resume by passing iter0).  Every
  * check_every steps the score -L(eps=0, beta=1, rho_scale=rhof) is read back
@@ -327,6 +328,83 @@ qg_status qg_debug_fetch(const qg_problem* prob, const void* d_workspace, const 
  */
 qg_status qg_time_stage(qg_problem* prob, const double* d_x, const qg_homotopy* h, int32_t stage,
                         int32_t reps, void* d_workspace, void* stream, double* mean_us);
+
+/*
+ * Contingency screening, the contingency solver of Alg. 2 (Section II-F,
+ * contingency backpropagation summary): screened steps score and
+ * backpropagate only a set of n_act contingencies, the worst set (the n_top
+ * most severe of the last exact step with severity above zeta) plus a
+ * uniform random draw from the rest.  The severity of contingency k is
+ * max_t (z_tk - d_t c_s beta (L - 1) eps), its penalty above the value it has
+ * with no overloaded branch (zero for an outage that overloads nothing).  In
+ * a screened evaluation a contingency outside the set takes that
+ * no-overload value in the per-period max and mean, and contributes no
+ * gradient.  One set serves every period.  Keys of the draw: output
+ * r 2^32 + k + 1 of SplitMix64 seeded with seed, r the refresh index.
+ *
+ * n_top = min(K, ceil(top_frac K)); n_act = min(K, n_top + ceil(rand_frac K)),
+ * which must be >= 1.  When fewer than n_top contingencies exceed zeta, the
+ * draw fills the remaining slots.  In qg_solve, step i (1-based iteration)
+ * is an exact step followed by a new selection (refresh index
+ * (i - 1) / refresh_every) when (i - 1) is a multiple of refresh_every or no
+ * set of n_act contingencies has been chosen yet; the other steps are
+ * screened.
+ */
+typedef struct qg_screen_opts {
+  double top_frac;         /* in [0, 1] */
+  double rand_frac;        /* in [0, 1] */
+  double zeta;             /* finite */
+  int32_t refresh_every;   /* >= 1 */
+  int32_t reserved;        /* 0 */
+  uint64_t seed;
+} qg_screen_opts;
+
+/* Bytes of the device screening buffer for these options.  Errors: ARG
+ * (options out of range, problem without contingencies). */
+qg_status qg_screen_bytes(const qg_problem* prob, const qg_screen_opts* opts, size_t* bytes);
+
+/*
+ * Turn screening on (opts non-NULL) or off (opts NULL; d_buf, bytes ignored).
+ * d_buf: caller-owned device buffer of at least qg_screen_bytes bytes,
+ * 256-byte aligned, used until screening is turned off or reconfigured (it
+ * holds the set, the severities and the set's outage factors gathered into
+ * contiguous columns).  No set is chosen yet: until one is, evaluations
+ * score every contingency.  A step graph cached by qg_solve is dropped.
+ * With screening on and a set chosen, qg_eval_grad and qg_time_stage
+ * evaluate the screened objective; qg_solve_batch and qg_solve with
+ * profile = 1 refuse a problem with screening on.
+ * Errors: ARG, STATE.
+ */
+qg_status qg_set_screening(qg_problem* prob, const qg_screen_opts* opts, void* d_buf,
+                           size_t bytes, void* stream);
+
+/*
+ * Exact evaluation at x (homotopy h; gradient discarded) followed by the
+ * selection with refresh index round >= 0 on the device: the severities,
+ * the set and its gathered outage factors.  Enqueued on the stream.
+ * Errors: ARG, STATE (screening off), DEVICE.
+ */
+qg_status qg_screen_refresh(qg_problem* prob, const double* d_x, const qg_homotopy* h,
+                            int64_t round, void* d_workspace, void* stream);
+
+/*
+ * Use the given set (host array of n strictly increasing positions into
+ * the contingency list, 1 <= n <= n_act of the options) for the screened
+ * evaluations until the next refresh.  Uploads it and gathers its outage
+ * factors; synchronises the stream.  Errors: ARG, STATE, DEVICE.
+ */
+qg_status qg_set_active_contingencies(qg_problem* prob, const int32_t* ks, int32_t n,
+                                      void* stream);
+
+/*
+ * Copy the current set (increasing positions into the contingency list) to
+ * host memory: *n receives its size, out needs capacity >= *n entries; and,
+ * if sev is non-NULL, the K severities of the last refresh (capacity >= K).
+ * Synchronises the stream.  Errors: ARG, STATE (screening off or no set),
+ * DEVICE.
+ */
+qg_status qg_get_active_contingencies(const qg_problem* prob, int32_t* out, int32_t capacity,
+                                      int32_t* n, double* sev, void* stream);
 
 void qg_destroy_problem(qg_problem* prob);
 const char* qg_status_string(qg_status s);

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqg.so")
 
-SOURCES = ["qg_api.hip", "qg_kernels.hip", "qg_mlp.hip", "qg_build.cpp"]
+SOURCES = ["qg_api.hip", "qg_kernels.hip", "qg_screen.hip", "qg_mlp.hip", "qg_build.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -2,6 +2,7 @@
 // graph capture of the solve loop and error plumbing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -41,6 +42,33 @@ qg_status check_problem(const qg_problem* pr) {
   if (!pr->alive) return fail(QG_ERR_STATE, "problem handle already destroyed");
   return QG_OK;
 }
+
+void drop_graph(qg::Problem& p) {
+  if (p.graph_exec) {
+    (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p.graph_exec));
+    p.graph_exec = nullptr;
+  }
+}
+
+// Set sizes of the screening options (Alg. 2): worst slots and slots in all.
+qg_status screen_counts(const qg::Problem& p, const qg_screen_opts* o, int* n_top, int* n_act) {
+  if (!o) return fail(QG_ERR_ARG, "null screening options");
+  if (p.K < 1) return fail(QG_ERR_ARG, "screening needs a problem with contingencies");
+  if (!(o->top_frac >= 0.0 && o->top_frac <= 1.0) || !(o->rand_frac >= 0.0 && o->rand_frac <= 1.0))
+    return fail(QG_ERR_ARG, "top_frac and rand_frac must lie in [0, 1]");
+  if (!std::isfinite(o->zeta)) return fail(QG_ERR_ARG, "zeta must be finite");
+  if (o->refresh_every < 1) return fail(QG_ERR_ARG, "refresh_every must be >= 1");
+  if (o->reserved != 0) return fail(QG_ERR_ARG, "reserved field must be 0");
+  const int nt = std::min(p.K, (int)std::ceil(o->top_frac * (double)p.K));
+  const int na = std::min(p.K, nt + (int)std::ceil(o->rand_frac * (double)p.K));
+  if (na < 1) return fail(QG_ERR_ARG, "the options select no contingency");
+  *n_top = nt;
+  *n_act = na;
+  return QG_OK;
+}
+
+// Evaluations score the chosen set once screening is on and a set exists.
+bool screened(const qg::Problem& p) { return p.scr.on && p.scr.chosen; }
 
 }  // namespace
 
@@ -132,10 +160,7 @@ qg_status qg_update_loads(qg_problem* pr, const double* load_p, const double* lo
   HIP_TRY(hipStreamSynchronize(st), "stream sync");
   p.dp.vload = lb.vload;
   // a cached step graph holds the old consumer value among its arguments
-  if (p.graph_exec) {
-    (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p.graph_exec));
-    p.graph_exec = nullptr;
-  }
+  drop_graph(p);
   return QG_OK;
 }
 
@@ -167,6 +192,130 @@ qg_status qg_problem_dims(const qg_problem* pr, int32_t* d, int32_t capacity) {
                          p.Kp, p.G16, p.G4,  p.Tp,      p.nLb,     p.nKb,     p.tile.bl,
                          p.tile.wl,   p.tile.tc, p.dp.lodf_kind};
   std::memcpy(d, v, sizeof(int32_t) * (capacity >= 17 ? 17 : 16));
+  return QG_OK;
+}
+
+qg_status qg_screen_bytes(const qg_problem* pr, const qg_screen_opts* o, size_t* bytes) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (!bytes) return fail(QG_ERR_ARG, "null output");
+  int nt = 0, na = 0;
+  s = screen_counts(pr->p, o, &nt, &na);
+  if (s != QG_OK) return s;
+  *bytes = qg::screen_bytes(pr->p, na);
+  return QG_OK;
+}
+
+qg_status qg_set_screening(qg_problem* pr, const qg_screen_opts* o, void* d_buf, size_t bytes,
+                           void* stream) {
+  (void)stream;
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  qg::Problem& p = pr->p;
+  if (!o) {
+    p.scr = qg::Screen{};
+    drop_graph(p);
+    return QG_OK;
+  }
+  int nt = 0, na = 0;
+  s = screen_counts(p, o, &nt, &na);
+  if (s != QG_OK) return s;
+  if (!d_buf || !aligned(d_buf)) return fail(QG_ERR_ARG, "screening buffer must be 256-byte aligned");
+  const size_t need = qg::screen_bytes(p, na);
+  if (bytes < need) return fail(QG_ERR_ARG, "screening buffer too small: need " + std::to_string(need));
+  qg::Screen sc;
+  qg::carve_screen(p, d_buf, na, &sc);
+  sc.on = true;
+  sc.chosen = false;
+  sc.n_top = nt;
+  sc.n_act = na;
+  sc.cap = na;
+  sc.Ka = (int)qg::round_up(na, qg::kCtgLanes);
+  sc.zeta = o->zeta;
+  sc.refresh = o->refresh_every;
+  sc.seed = o->seed;
+  p.scr = sc;
+  drop_graph(p);
+  return QG_OK;
+}
+
+qg_status qg_screen_refresh(qg_problem* pr, const double* d_x, const qg_homotopy* h,
+                            int64_t round, void* d_workspace, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  qg::Problem& p = pr->p;
+  if (!p.scr.on) return fail(QG_ERR_STATE, "screening is off");
+  if (!d_x || !h || !d_workspace) return fail(QG_ERR_ARG, "null x, homotopy or workspace");
+  if (!aligned(d_x) || !aligned(d_workspace))
+    return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
+  if (round < 0) return fail(QG_ERR_ARG, "round must be >= 0");
+  if (!(h->eps >= 0.0) || !(h->beta >= 0.0) || !(h->rho_scale >= 0.0) || !std::isfinite(h->eps) ||
+      !std::isfinite(h->beta) || !std::isfinite(h->rho_scale))
+    return fail(QG_ERR_ARG, "homotopy values must be finite and non-negative");
+  qg::DevWork w = qg::carve_workspace(&p, d_workspace);
+  qg::EvalMode m{};
+  m.schedule = 0;
+  m.eps = h->eps;
+  m.beta = h->beta;
+  m.rho_s = h->rho_scale;
+  if (p.scr.n_act != p.scr.cap) drop_graph(p);
+  p.scr.n_act = p.scr.cap;
+  p.scr.Ka = (int)qg::round_up(p.scr.cap, qg::kCtgLanes);
+  int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, m, 0, nullptr, nullptr, stream, nullptr);
+  if (e == 0) e = qg::launch_screen_select(&p, w, round, stream);
+  if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+  p.scr.chosen = true;
+  return QG_OK;
+}
+
+qg_status qg_set_active_contingencies(qg_problem* pr, const int32_t* ks, int32_t n,
+                                      void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  qg::Problem& p = pr->p;
+  if (!p.scr.on) return fail(QG_ERR_STATE, "screening is off");
+  if (!ks || n < 1 || n > p.scr.cap)
+    return fail(QG_ERR_ARG, "need 1 <= n <= " + std::to_string(p.scr.cap) + " contingencies");
+  for (int i = 0; i < n; ++i)
+    if (ks[i] < 0 || ks[i] >= p.K || (i > 0 && ks[i] <= ks[i - 1]))
+      return fail(QG_ERR_ARG, "positions must be strictly increasing in [0, K)");
+  std::vector<int32_t> act(p.Kp, 0), slot(p.Kp, -1);
+  for (int i = 0; i < n; ++i) {
+    act[i] = ks[i];
+    slot[ks[i]] = i;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");  // earlier steps may still read the set
+  HIP_TRY(hipMemcpyAsync(p.scr.act_k, act.data(), act.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st), "set upload");
+  HIP_TRY(hipMemcpyAsync(p.scr.act_slot, slot.data(), slot.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st), "set upload");
+  if (n != p.scr.n_act) drop_graph(p);
+  p.scr.n_act = n;
+  p.scr.Ka = (int)qg::round_up(n, qg::kCtgLanes);
+  if (qg::launch_screen_gather(&p, st) != 0) return hip_fail(hipGetLastError(), "kernel launch");
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  p.scr.chosen = true;
+  return QG_OK;
+}
+
+qg_status qg_get_active_contingencies(const qg_problem* pr, int32_t* out, int32_t capacity,
+                                      int32_t* n, double* sev, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  const qg::Problem& p = pr->p;
+  if (!p.scr.on || !p.scr.chosen) return fail(QG_ERR_STATE, "screening is off or no set chosen");
+  if (!out || !n) return fail(QG_ERR_ARG, "null output");
+  if (capacity < p.scr.n_act) return fail(QG_ERR_ARG, "output too small");
+  if (sev && capacity < p.K) return fail(QG_ERR_ARG, "severities need capacity >= K");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(out, p.scr.act_k, (size_t)p.scr.n_act * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, st), "set read");
+  if (sev)
+    HIP_TRY(hipMemcpyAsync(sev, p.scr.sev, (size_t)p.K * sizeof(double), hipMemcpyDeviceToHost, st),
+            "severity read");
+  HIP_TRY(hipStreamSynchronize(st), "stream sync");
+  *n = p.scr.n_act;
   return QG_OK;
 }
 
@@ -216,6 +365,7 @@ qg_status qg_eval_grad(qg_problem* pr, const double* d_x, double* d_grad, double
   m.eps = h->eps;
   m.beta = h->beta;
   m.rho_s = h->rho_scale;
+  m.screened = screened(p) ? 1 : 0;
   int e = qg::launch_eval(&p, w, d_x, d_grad, d_terms, m, 0, nullptr, nullptr, stream, nullptr);
   if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
   return QG_OK;
@@ -240,6 +390,7 @@ qg_status qg_time_stage(qg_problem* pr, const double* d_x, const qg_homotopy* h,
   m.eps = h->eps;
   m.beta = h->beta;
   m.rho_s = h->rho_scale;
+  m.screened = screened(p) ? 1 : 0;
   double ms = 0.0;
   int e = qg::time_stage(&p, w, d_x, m, stage, reps, stream, &ms);
   if (e != 0) return hip_fail((hipError_t)e, "stage timing");
@@ -319,9 +470,13 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     return fail(QG_ERR_ARG, "device buffers must be 256-byte aligned");
   s = check_solve_opts(o, cfg);
   if (s != QG_OK) return s;
+  if (o->profile && pr->p.scr.on)
+    return fail(QG_ERR_ARG, "profile mode times the exact step: turn screening off");
   const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
 
   const qg::Problem& p = pr->p;
+  const bool scr = p.scr.on;
+  const int64_t R = scr ? p.scr.refresh : 0;
   qg::DevWork w = qg::carve_workspace(&p, d_workspace);
   hipStream_t user = static_cast<hipStream_t>(stream);
   hipStream_t ex = user ? user : pr->own;
@@ -341,6 +496,10 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   sm.schedule = 1;
   sm.adam_b1 = cfg->beta1; sm.adam_b2 = cfg->beta2; sm.adam_eps = cfg->eps;
   sm.eps_in_num = cfg->eps_in_numerator;
+  // screened steps (the graph holds these when screening is on); exact steps
+  // with a refresh of the set in between
+  qg::EvalMode sm_run = sm;
+  sm_run.screened = scr ? 1 : 0;
 
   std::vector<double> table((size_t)qg::kSchedCap * qg::kSchedStride, 0.0);
   auto upload = [&](int64_t first, int count) -> qg_status {
@@ -375,15 +534,25 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   // graph of gsteps consecutive steps (the step counter lives on the device);
   // one graph launch costs about as much as several kernels, so it covers
   // up to 32 steps
-  const int gsteps = (int)std::min<int64_t>(32, o->n_steps);
-  hipGraphExec_t gexec = static_cast<hipGraphExec_t>(pr->p.graph_exec);
+  int gsteps = (int)std::min<int64_t>(32, o->n_steps);
+  if (scr) gsteps = (int)std::min<int64_t>(gsteps, R - 1);
+  if (scr && pr->p.scr.n_act != pr->p.scr.cap) {
+    // a smaller set given by the caller: the solve works with full-size sets,
+    // chosen afresh at its first step
+    pr->p.scr.chosen = false;
+    pr->p.scr.n_act = pr->p.scr.cap;
+    pr->p.scr.Ka = (int)qg::round_up(pr->p.scr.cap, qg::kCtgLanes);
+    drop_graph(pr->p);
+  }
+  hipGraphExec_t gexec = nullptr;  // used only when it holds this call's steps
   if (graph && gsteps >= 4) {
+    gexec = static_cast<hipGraphExec_t>(pr->p.graph_exec);
     const void* key[5] = {d_x, d_m, d_v, d_workspace, nullptr};
     bool hit = gexec && std::memcmp(key, pr->p.graph_key, sizeof(key)) == 0 &&
                pr->p.graph_steps == gsteps;
     // the schedule constants are kernel arguments, so a different schedule
     // needs a new capture as well
-    if (hit && std::memcmp(&pr->p.graph_mode, &sm, sizeof(sm)) != 0) hit = false;
+    if (hit && std::memcmp(&pr->p.graph_mode, &sm_run, sizeof(sm_run)) != 0) hit = false;
     // and so is the contingency tile (grid and LDS size of the map-reduce)
     const qg::CtgTile& gt = pr->p.graph_tile;
     if (hit && (gt.bl != p.tile.bl || gt.wl != p.tile.wl || gt.tc != p.tile.tc)) hit = false;
@@ -392,7 +561,7 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(pr->own, hipStreamCaptureModeThreadLocal), "begin capture");
       for (int k = 0; k < gsteps; ++k)
-        qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, pr->own, nullptr);
+        qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
       HIP_TRY(hipStreamEndCapture(pr->own, &g), "end capture");
       hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
@@ -400,10 +569,39 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
       pr->p.graph_exec = gexec;
       std::memcpy(pr->p.graph_key, key, sizeof(key));
       pr->p.graph_steps = gsteps;
-      std::memcpy(&pr->p.graph_mode, &sm, sizeof(sm));
+      std::memcpy(&pr->p.graph_mode, &sm_run, sizeof(sm_run));
       pr->p.graph_tile = p.tile;
     }
   }
+
+  // screening: steps [done0, done0 + n) of this call, the step of iteration
+  // index it = iter0 + done (0-based) exact and followed by a selection when
+  // it is a multiple of R or no set exists yet
+  auto run_screened = [&](int64_t done0, int64_t n) -> qg_status {
+    int64_t k = 0;
+    while (k < n) {
+      const int64_t it = o->iter0 + done0 + k;
+      if (it % R == 0 || !pr->p.scr.chosen) {
+        pr->p.scr.n_act = pr->p.scr.cap;
+        pr->p.scr.Ka = (int)qg::round_up(pr->p.scr.cap, qg::kCtgLanes);
+        int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, ex, nullptr);
+        if (e == 0) e = qg::launch_screen_select(&p, w, it / R, ex);
+        if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+        pr->p.scr.chosen = true;
+        ++k;
+        continue;
+      }
+      int64_t len = std::min(n - k, R - it % R);
+      if (graph && gexec)
+        for (; len >= gsteps; len -= gsteps, k += gsteps)
+          HIP_TRY(hipGraphLaunch(gexec, ex), "graph launch");
+      for (; len > 0; --len, ++k) {
+        int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, ex, nullptr);
+        if (e != 0) return hip_fail((hipError_t)e, "kernel launch");
+      }
+    }
+    return QG_OK;
+  };
 
   auto run_steps = [&](int64_t n) -> qg_status {
     int64_t left = n;
@@ -458,7 +656,7 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     n = std::min<int64_t>(n, qg::kSchedCap);
     s = upload(o->iter0 + done + 1, (int)n);
     if (s != QG_OK) return s;
-    s = run_steps(n);
+    s = scr ? run_screened(done, n) : run_steps(n);
     if (s != QG_OK) return s;
     done += n;
     if (o->check_every > 0 && (done % o->check_every == 0) && o->z_ed > 0.0) {
@@ -512,6 +710,8 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
       return fail(QG_ERR_ARG, "null or misaligned buffer of scenario " + std::to_string(i));
     for (int j = 0; j < i; ++j)
       if (probs[j] == probs[i]) return fail(QG_ERR_ARG, "a problem appears twice in the batch");
+    if (probs[i]->p.scr.on)
+      return fail(QG_ERR_ARG, "batched solves score every contingency: turn screening off");
   }
   const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
   std::vector<qg::DevWork> w(n);

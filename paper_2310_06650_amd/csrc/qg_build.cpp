@@ -690,4 +690,43 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   return w;
 }
 
+// Screening buffer: act_k, act_slot, top, sel [Kp] int32; sev [Kp] double;
+// key [Kp] uint64; then the gathered outage factors [Lp][cap padded to 64]
+// in the problem's factor storage.  Each part 256-byte aligned.
+namespace {
+struct ScreenLayout {
+  size_t off[7];
+  size_t total;
+};
+ScreenLayout screen_layout(const Problem& p, int cap) {
+  const size_t Kp = (size_t)p.Kp;
+  const size_t ka = (size_t)round_up(cap, kCtgLanes);
+  const size_t cnt[7] = {Kp * 4, Kp * 4, Kp * 4, Kp * 4, Kp * 8, Kp * 8,
+                         (size_t)p.Lp * ka * lodf_elem_bytes(lodf_kind_of(p.flags))};
+  ScreenLayout sl;
+  size_t o = 0;
+  for (int i = 0; i < 7; ++i) {
+    sl.off[i] = o;
+    o += (size_t)round_up((int64_t)cnt[i], kAlign);
+  }
+  sl.total = o;
+  return sl;
+}
+}  // namespace
+
+size_t screen_bytes(const Problem& p, int cap) { return screen_layout(p, cap).total; }
+
+void carve_screen(const Problem& p, void* buf, int cap, Screen* sc) {
+  const ScreenLayout sl = screen_layout(p, cap);
+  unsigned char* b = static_cast<unsigned char*>(buf);
+  sc->act_k = reinterpret_cast<int*>(b + sl.off[0]);
+  sc->act_slot = reinterpret_cast<int*>(b + sl.off[1]);
+  sc->top = reinterpret_cast<int*>(b + sl.off[2]);
+  sc->sel = reinterpret_cast<int*>(b + sl.off[3]);
+  sc->sev = reinterpret_cast<double*>(b + sl.off[4]);
+  sc->key = reinterpret_cast<uint64_t*>(b + sl.off[5]);
+  sc->lodf_act = b + sl.off[6];
+  sc->bytes = sl.total;
+}
+
 }  // namespace qg

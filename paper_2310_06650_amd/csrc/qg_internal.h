@@ -23,6 +23,10 @@ constexpr int kSchedStride = 16;        // doubles per step in the schedule tabl
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Parameter block layout (DevWork::params): the homotopy and step sizes of
+// the step being evaluated.
+enum ParamSlot { PB_EPS = 0, PB_BETA = 1, PB_RHO = 2, PB_ALPHA = 4, PB_BC1 = 10, PB_BC2 = 11 };
+
 // Storage kind of the outage factors, from the build flags.
 enum LodfKind { kLodfF64 = 0, kLodfF32 = 1, kLodfBF16 = 2 };
 inline int lodf_kind_of(uint32_t flags) {
@@ -124,7 +128,37 @@ struct EvalMode {
   double eps0, epsf, beta0, betaf, rho0, rhof;
   double adam_b1, adam_b2, adam_eps;
   int eps_in_num;
+  int screened;          // 1: score only the problem's chosen contingency set
 };
+
+struct Problem;
+
+// Contingency screening (Alg. 2): the set of contingencies scored by the
+// screened steps, and its outage factors gathered into contiguous columns.
+// All device arrays live in the caller's screening buffer.
+struct Screen {
+  bool on = false;
+  bool chosen = false;       // a set has been selected or given
+  int n_top = 0;             // worst-set slots
+  int n_act = 0;             // contingencies scored (slots in use)
+  int cap = 0;               // most slots the buffer holds
+  int Ka = 0;                // n_act padded to 64: row stride of lodf_act
+  double zeta = 0.0;         // severity threshold of the worst set
+  int refresh = 0;           // steps between exact refresh steps in qg_solve
+  uint64_t seed = 0;         // seed of the random draw
+  int* act_k = nullptr;      // [Kp] slot -> contingency (0 past n_act)
+  int* act_slot = nullptr;   // [Kp] contingency -> slot, -1 if not scored
+  int* top = nullptr;        // [Kp] worst-set flags of the last selection
+  int* sel = nullptr;        // [Kp] chosen flags of the last selection
+  double* sev = nullptr;     // [Kp] severities of the last refresh
+  uint64_t* key = nullptr;   // [Kp] draw keys of the last refresh
+  void* lodf_act = nullptr;  // [Lp][Ka] outage factors of the slots, NaN past n_act
+  size_t bytes = 0;          // bytes of the buffer in use
+};
+// Bytes of a screening buffer for up to cap scored contingencies, and the
+// carve of one (sets the pointers of sc).
+size_t screen_bytes(const Problem& p, int cap);
+void carve_screen(const Problem& p, void* buf, int cap, Screen* sc);
 
 struct Problem {
   // sizes
@@ -159,6 +193,7 @@ struct Problem {
   std::vector<double> rsum_host; // [Lp] ISF row sums
   std::vector<double> dt_host;   // [T]
   double load_value = 0.0;
+  Screen scr;
 };
 
 // Host build products (before upload).
@@ -203,5 +238,10 @@ int launch_adam(const Problem* p, double* x, double* m, double* v, const double*
                 double b2, double eps, int eps_in_num, void* stream);
 int launch_set_step(const Problem* p, const DevWork& w, int64_t value, void* stream);
 int launch_check_finite(const Problem* p, const double* x, int* flag, void* stream);
+// Screening (qg_screen.hip): choose the set from the severities of the last
+// exact evaluation (its z_tk and homotopy in the workspace), then gather its
+// outage factors; or gather only, for a set uploaded by the host.
+int launch_screen_select(const Problem* p, const DevWork& w, int64_t round, void* stream);
+int launch_screen_gather(const Problem* p, void* stream);
 
 }  // namespace qg

@@ -39,9 +39,6 @@ struct StepParams {
   double bc1, bc2;
 };
 
-// Parameter block layout (DevWork::params)
-enum { PB_EPS = 0, PB_BETA = 1, PB_RHO = 2, PB_ALPHA = 4, PB_BC1 = 10, PB_BC2 = 11 };
-
 struct EvalArgs {
   DevProblem p;
   DevWork w;
@@ -55,6 +52,14 @@ struct EvalArgs {
   int nb_br, nb_bus, bus_chunks, nb_gen, nsplit;
   int nLb, nKb, nKc, nLc, tc;
   TermOffsets toff;
+  // contingencies scored this step (Alg. 2): slot s of the map-reduce holds
+  // contingency act_k[s] (the identity when act_k is null), na slots in use,
+  // outage factors of the slots in rows of kst entries at lodf_sel;
+  // act_slot maps a contingency back to its slot (-1 when not scored)
+  const int* act_k;
+  const int* act_slot;
+  int na, kst;
+  const void* lodf_sel;
 };
 
 // ---------------------------------------------------------------------------
@@ -756,13 +761,13 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
   const int nt = min(TC, T - t0);
   const int lbase = __builtin_amdgcn_readfirstlane(lb * BL * WL + wv * BL);
   const bool on = lbase < Lp;
-  const int k = kb * 64 + lane;
+  const int k = kb * 64 + lane;  // slot of the lane
   double* sFk = dyn;
   double* zsh = dyn + TC * 64;
   double* ssh = zsh + TC * WL * 64;
   for (int e = threadIdx.x; e < nt * 64; e += blockDim.x) {
-    const int tt = e >> 6, kk = e & 63;
-    sFk[e] = w.Fk[(size_t)(t0 + tt) * Kp + kb * 64 + kk];
+    const int tt = e >> 6, s = kb * 64 + (e & 63);
+    sFk[e] = w.Fk[(size_t)(t0 + tt) * Kp + (a.act_k ? a.act_k[s] : s)];
   }
   const cdouble* Sc = as_const(p.ctg_smax2);
   const cdouble* Mc = as_const(p.ctg_smax);
@@ -777,7 +782,7 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
   if (on) {
 #pragma unroll
     for (int j = 0; j < BL; ++j) {
-      lod[j] = lodf_load(lodf, (size_t)(lbase + j) * Kp + k);
+      lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
       smx2[j] = (R)Sc[lbase + j];
     }
     const int et = lane >> 3, eg = lane & 7;
@@ -869,16 +874,17 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   const int T = p.T, L = p.L, K = p.K, Kp = p.Kp;
   const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
   const double kt = p.dt[t] * p.c_s * beta;
-  const int k = kc * 64 + lane;
-  const size_t o = (size_t)t * Kp + k;
+  const int s = kc * 64 + lane;  // slot
+  const size_t o = (size_t)t * Kp + s;
   const size_t stride = (size_t)T * Kp;
   const double zs = strided_sum<16>(w.zpart + o, a.nLb, stride);
   const double ss = strided_sum<16>(w.spart + o, a.nLb, stride);
   double z = -DBL_MAX, zsum = 0.0;
   int idx = INT_MAX;
-  if (k < K) {
+  if (s < a.na) {
+    const int k = a.act_k ? a.act_k[s] : s;
     z = kt * ((double)(L - 1) * eps + zs);
-    w.zval[o] = z;
+    w.zval[(size_t)t * Kp + k] = z;
     w.smean[o] = ss / (double)K;
     idx = k;
     zsum = z;
@@ -967,11 +973,16 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
           sacc[0] = lo * dP;
         }
       }
-      if (kk >= 0) r += w.smean[(size_t)t * Kp + kk];
+      if (kk >= 0) {
+        const int sl = a.act_slot ? a.act_slot[kk] : kk;
+        if (sl >= 0) r += w.smean[(size_t)t * Kp + sl];
+      }
     }
     if (lc == 0 && tid == 0) {
       w.tpart[a.toff.cmax + t] = zmax;
-      w.tpart[a.toff.cmean + t] = zsum * invK;
+      // contingencies not scored this step take their no-overload penalty
+      const double rest = (double)(K - a.na) * (kt * ((double)(L - 1) * eps));
+      w.tpart[a.toff.cmean + t] = (zsum + rest) * invK;
       w.kstar[t] = (double)kstar;
     }
   } else if (lc == 0 && tid == 0) {
@@ -1264,6 +1275,23 @@ static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, 
   a.nLc = pr->nLc;
   a.tc = pr->tile.tc;
   a.toff = pr->toff;
+  const Screen& sc = pr->scr;
+  if (mode.screened) {
+    a.act_k = sc.act_k;
+    a.act_slot = sc.act_slot;
+    a.na = sc.n_act;
+    a.kst = sc.Ka;
+    a.nKb = a.nKc = sc.Ka / kCtgLanes;
+    a.lodf_sel = sc.lodf_act;
+  } else {
+    a.act_k = nullptr;
+    a.act_slot = nullptr;
+    a.na = pr->K;
+    a.kst = pr->Kp;
+    const DevProblem& dp = pr->dp;
+    a.lodf_sel = dp.lodf_kind == kLodfF64 ? (const void*)dp.lodf
+                 : dp.lodf_kind == kLodfF32 ? (const void*)dp.lodf32 : (const void*)dp.lodf16;
+  }
   return a;
 }
 
@@ -1276,15 +1304,18 @@ static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStr
     case 1:
       if (pr->K > 0) {
         const int ntc = (pr->T + pr->tile.tc - 1) / pr->tile.tc;
-        const dim3 grid(pr->nLb, pr->nKb, ntc), block(64 * pr->tile.wl);
-        const DevProblem& dp = pr->dp;
-        if (dp.lodf_kind == kLodfF64) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf);
-        else if (dp.lodf_kind == kLodfF32) launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf32);
-        else launch_ctg_main(pr->tile.bl, grid, block, s, a, dp.lodf16);
+        const dim3 grid(pr->nLb, a.nKb, ntc), block(64 * pr->tile.wl);
+        const int kind = pr->dp.lodf_kind;
+        if (kind == kLodfF64)
+          launch_ctg_main(pr->tile.bl, grid, block, s, a, static_cast<const double*>(a.lodf_sel));
+        else if (kind == kLodfF32)
+          launch_ctg_main(pr->tile.bl, grid, block, s, a, static_cast<const float*>(a.lodf_sel));
+        else
+          launch_ctg_main(pr->tile.bl, grid, block, s, a, static_cast<const uint16_t*>(a.lodf_sel));
       }
       break;
     case 2:
-      if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(pr->nKc, pr->T), dim3(64), 0, s, a);
+      if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(a.nKc, pr->T), dim3(64), 0, s, a);
       break;
     case 3:
       hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0, s, a);

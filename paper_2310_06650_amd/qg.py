@@ -108,6 +108,11 @@ class qg_solve_report(C.Structure):
                 ("kernel_calls", C.c_int64 * QG_NKERNELS)]
 
 
+class qg_screen_opts(C.Structure):
+    _fields_ = [("top_frac", C.c_double), ("rand_frac", C.c_double), ("zeta", C.c_double),
+                ("refresh_every", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
 QG_MLP_MAX_DEPTH = 8
 
 
@@ -143,6 +148,11 @@ _sig = {
     "qg_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
                                  C.POINTER(_vp), C.POINTER(_vp), C.POINTER(qg_solve_opts),
                                  C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp]),
+    "qg_screen_bytes": (C.c_int, [_vp, C.POINTER(qg_screen_opts), C.POINTER(C.c_size_t)]),
+    "qg_set_screening": (C.c_int, [_vp, C.POINTER(qg_screen_opts), _vp, C.c_size_t, _vp]),
+    "qg_screen_refresh": (C.c_int, [_vp, _vp, C.POINTER(qg_homotopy), C.c_int64, _vp, _vp]),
+    "qg_set_active_contingencies": (C.c_int, [_vp, _pi, C.c_int32, _vp]),
+    "qg_get_active_contingencies": (C.c_int, [_vp, _pi, C.c_int32, _pi, _pd, _vp]),
     "qg_destroy_problem": (None, [_vp]),
     "qg_mlp_sizes": (C.c_int, [C.POINTER(qg_mlp_desc), C.c_int32, C.POINTER(qg_mlp_layout),
                                C.POINTER(C.c_size_t)]),
@@ -404,6 +414,46 @@ class Problem:
         cfg = cfg or adam_cfg()
         return qg_solve(self.handle, x.data_ptr(), m.data_ptr(), v.data_ptr(), opts, cfg,
                         self.workspace.data_ptr(), self._stream())
+
+    # ---- contingency screening (Alg. 2)
+
+    def set_screening(self, top_frac=None, rand_frac=0.0, zeta=0.0, refresh=10, seed=0):
+        """Screen contingencies (top_frac None: back to scoring all of them)."""
+        if top_frac is None:
+            _check(lib.qg_set_screening(self.handle, None, None, 0, self._stream()),
+                   "qg_set_screening")
+            self.screen_buf = None
+            return
+        o = qg_screen_opts(top_frac=top_frac, rand_frac=rand_frac, zeta=zeta,
+                           refresh_every=refresh, reserved=0, seed=seed)
+        nb = C.c_size_t(0)
+        _check(lib.qg_screen_bytes(self.handle, C.byref(o), C.byref(nb)), "qg_screen_bytes")
+        buf = self.torch.empty(max(nb.value, 256), dtype=self.torch.uint8, device=self.device)
+        _check(lib.qg_set_screening(self.handle, C.byref(o), buf.data_ptr(), nb.value,
+                                    self._stream()), "qg_set_screening")
+        self.screen_buf = buf   # the library uses it until screening is reconfigured
+
+    def screen_refresh(self, x, eps, beta=1.0, rho_scale=1.0, round=0):
+        _check(lib.qg_screen_refresh(self.handle, x.data_ptr(), C.byref(qg_homotopy(
+            eps, beta, rho_scale)), int(round), self.workspace.data_ptr(), self._stream()),
+            "qg_screen_refresh")
+
+    def set_active_contingencies(self, ks):
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        _check(lib.qg_set_active_contingencies(self.handle, ks.ctypes.data_as(_pi), ks.size,
+                                               self._stream()), "qg_set_active_contingencies")
+
+    def active_contingencies(self, severities=False):
+        """The current set (and the severities of the last refresh)."""
+        out = np.zeros(max(self.K, 1), dtype=np.int32)
+        n = C.c_int32(0)
+        sev = np.zeros(max(self.K, 1), dtype=np.float64) if severities else None
+        _check(lib.qg_get_active_contingencies(
+            self.handle, out.ctypes.data_as(_pi), out.size, C.byref(n),
+            sev.ctypes.data_as(_pd) if sev is not None else None, self._stream()),
+            "qg_get_active_contingencies")
+        ks = out[:n.value].astype(np.int64)
+        return (ks, sev[:self.K]) if severities else ks
 
     def fetch(self, name, shape):
         out = np.empty(shape, dtype=np.float64)

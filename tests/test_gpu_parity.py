@@ -214,9 +214,9 @@ def test_solve_trajectory_c1(qg):
     loop grows to ~1e-2 in x by step 200 (Adam's normalised steps flip sign
     where a gradient oscillates around zero).  So (a) the free-running
     trajectories agree to 1e-9 over the first 50 steps, where that noise is
-    still below 1e-13, and (b) every one of the 200 steps is checked by
-    shadowing: the oracle's step taken from the GPU's own state (x, m, v)
-    must match the GPU's next state to 1e-9.
+    still below 1e-13, and (b) every one of the 200 steps is checked from the
+    oracle's own trajectory: the GPU's step taken from the oracle's state
+    (x, m, v) before step i must match the oracle's state after it to 1e-9.
     """
     import torch
     c = case("c1")
@@ -225,30 +225,32 @@ def test_solve_trajectory_c1(qg):
     n = 200
     sopt = _sched_opts(n, [1e-3] * 6, [1e-3] * 6)
     x0 = synth.flat_start(c)
-    rec = []
-    osolve.run(m, x0, 50, sopt, record=rec)
-    xd = prob.new_vector(x0)
-    md = prob.new_vector()
-    vd = prob.new_vector()
+    lo, hi = oadam.box_bounds(c)
+    states = [(x0.copy(), np.zeros_like(x0), np.zeros_like(x0))]
+    for i in range(n):
+        xp, mp, vp = states[-1]
+        eps, beta, rho, alpha = osolve.schedule(i + 1, n, sopt)
+        _, g = ob.evaluate(m, xp, eps, beta, rho)
+        states.append(oadam.adam_update(xp, mp, vp, g, i + 1, osolve.class_vector(c, alpha),
+                                        lo, hi))
     common = dict(n_total=n, eps0=sopt["eps0"], epsf=sopt["epsf"], beta0=0.5, betaf=1.0,
                   rho0=0.5, rhof=1.0, use_graph=0)
-    lo, hi = oadam.box_bounds(c)
-    x_prev = x0.copy()
-    m_prev = np.zeros_like(x0)
-    v_prev = np.zeros_like(x0)
-    for i in range(n):
+    # (a) free running
+    xd, md, vd = prob.new_vector(x0), prob.new_vector(), prob.new_vector()
+    for i in range(50):
         prob.solve(xd, md, vd, qg.solve_opts(1, [1e-3] * 6, iter0=i, **common))
         torch.cuda.synchronize()
-        xi, mi, vi = (t.cpu().numpy() for t in (xd, md, vd))
-        if i < 50:
-            assert np.abs(xi - rec[i]).max() <= 1e-9 * np.abs(rec[i]).max(), ("free", i)
-        eps, beta, rho, alpha = osolve.schedule(i + 1, n, sopt)
-        _, g = ob.evaluate(m, x_prev, eps, beta, rho)
-        xs, ms, vs = oadam.adam_update(x_prev, m_prev, v_prev, g, i + 1,
-                                       osolve.class_vector(c, alpha), lo, hi)
-        assert np.abs(xi - xs).max() <= 1e-9 * np.abs(xs).max(), ("shadow x", i)
-        assert np.abs(mi - ms).max() <= 1e-9 * np.abs(ms).max(), ("shadow m", i)
-        x_prev, m_prev, v_prev = xi, mi, vi
+        xi, xr = xd.cpu().numpy(), states[i + 1][0]
+        assert np.abs(xi - xr).max() <= 1e-9 * np.abs(xr).max(), ("free", i)
+    # (b) one GPU step from each oracle state
+    for i in range(n):
+        for dst, src in zip((xd, md, vd), states[i]):
+            dst.copy_(torch.from_numpy(src))
+        prob.solve(xd, md, vd, qg.solve_opts(1, [1e-3] * 6, iter0=i, **common))
+        torch.cuda.synchronize()
+        xs, ms, _ = states[i + 1]
+        assert np.abs(xd.cpu().numpy() - xs).max() <= 1e-9 * np.abs(xs).max(), ("step x", i)
+        assert np.abs(md.cpu().numpy() - ms).max() <= 1e-9 * np.abs(ms).max(), ("step m", i)
 
 
 def test_graph_replay_equals_eager(qg):
