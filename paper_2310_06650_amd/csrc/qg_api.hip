@@ -25,6 +25,8 @@ namespace {
 
 using qg::fail;
 
+constexpr int kCycleMax = 128;  // longest refresh cycle captured as one graph
+
 bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % qg::kAlign) == 0; }
 
 qg_status hip_fail(hipError_t e, const char* what) {
@@ -439,6 +441,7 @@ static void fill_schedule(double* table, const qg_solve_opts* o, const qg_adam_c
       row[3 + c] = o->alpha0[c] * std::pow(10.0, sc * std::log10(o->alphaf[c] / o->alpha0[c]));
     row[9] = 1.0 - std::pow(cfg->beta1, i);
     row[10] = 1.0 - std::pow(cfg->beta2, i);
+    row[11] = i - 1.0;  // 0-based iteration index (refresh index of screening)
   }
 }
 
@@ -535,7 +538,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   // one graph launch costs about as much as several kernels, so it covers
   // up to 32 steps
   int gsteps = (int)std::min<int64_t>(32, o->n_steps);
-  if (scr) gsteps = (int)std::min<int64_t>(gsteps, R - 1);
+  // screening: one graph per refresh cycle (the exact step, the selection and
+  // the R - 1 screened steps), so the refresh adds no launch gaps
+  if (scr) gsteps = (R >= 2 && R <= kCycleMax && o->n_steps >= R) ? (int)R : 0;
   if (scr && pr->p.scr.n_act != pr->p.scr.cap) {
     // a smaller set given by the caller: the solve works with full-size sets,
     // chosen afresh at its first step
@@ -560,8 +565,15 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; pr->p.graph_exec = nullptr; }
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(pr->own, hipStreamCaptureModeThreadLocal), "begin capture");
-      for (int k = 0; k < gsteps; ++k)
-        qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+      if (scr) {
+        qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, pr->own, nullptr);
+        qg::launch_screen_select(&p, w, -1, pr->own);
+        for (int k = 1; k < gsteps; ++k)
+          qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+      } else {
+        for (int k = 0; k < gsteps; ++k)
+          qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+      }
       HIP_TRY(hipStreamEndCapture(pr->own, &g), "end capture");
       hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
@@ -581,6 +593,12 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     int64_t k = 0;
     while (k < n) {
       const int64_t it = o->iter0 + done0 + k;
+      if (gexec && it % R == 0 && n - k >= R) {
+        HIP_TRY(hipGraphLaunch(gexec, ex), "graph launch");
+        pr->p.scr.chosen = true;
+        k += R;
+        continue;
+      }
       if (it % R == 0 || !pr->p.scr.chosen) {
         pr->p.scr.n_act = pr->p.scr.cap;
         pr->p.scr.Ka = (int)qg::round_up(pr->p.scr.cap, qg::kCtgLanes);
@@ -592,9 +610,6 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
         continue;
       }
       int64_t len = std::min(n - k, R - it % R);
-      if (graph && gexec)
-        for (; len >= gsteps; len -= gsteps, k += gsteps)
-          HIP_TRY(hipGraphLaunch(gexec, ex), "graph launch");
       for (; len > 0; --len, ++k) {
         int e = qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, ex, nullptr);
         if (e != 0) return hip_fail((hipError_t)e, "kernel launch");

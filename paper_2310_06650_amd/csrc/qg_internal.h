@@ -240,7 +240,8 @@ int launch_set_step(const Problem* p, const DevWork& w, int64_t value, void* str
 int launch_check_finite(const Problem* p, const double* x, int* flag, void* stream);
 // Screening (qg_screen.hip): choose the set from the severities of the last
 // exact evaluation (its z_tk and homotopy in the workspace), then gather its
-// outage factors; or gather only, for a set uploaded by the host.
+// outage factors; or gather only, for a set uploaded by the host.  round < 0:
+// the refresh index follows from the schedule row of the step just taken.
 int launch_screen_select(const Problem* p, const DevWork& w, int64_t round, void* stream);
 int launch_screen_gather(const Problem* p, void* stream);
 

@@ -8,7 +8,7 @@
 //                  outage that overloads nothing), and the draw key of k
 //   k_scr_top      worst set: contingencies with sev_k > zeta ranked by
 //                  decreasing severity (smaller index first on ties); ranks
-//                  by counting, every lane against all K staged through LDS
+//                  by counting, every lane against all K
 //   k_scr_draw     the other slots go to the contingencies outside the worst
 //                  set with the smallest keys (smaller index first on ties):
 //                  a uniform draw without replacement
@@ -39,14 +39,21 @@ __device__ __forceinline__ uint64_t splitmix_key(uint64_t seed, uint64_t r, int 
   return z ^ (z >> 31);
 }
 
+// r_arg >= 0: refresh index r_arg; otherwise it follows from the solve
+// schedule: the row of the step just taken holds its 0-based iteration index,
+// and r = index / refresh.
 __global__ __launch_bounds__(kScrBlock) void k_scr_sev(DevProblem p, const double* zval,
-                                                       const double* params, uint64_t seed,
-                                                       uint64_t r, double* sev, uint64_t* key) {
+                                                       const double* params, const double* sched,
+                                                       const int64_t* step, int64_t refresh,
+                                                       uint64_t seed, int64_t r_arg, double* sev,
+                                                       uint64_t* key) {
   // the no-overload value is formed exactly as in the per-contingency
   // reduction, so an outage without overload has severity exactly zero
 #pragma clang fp contract(off)
   const int k = blockIdx.x * kScrBlock + threadIdx.x;
   if (k >= p.K) return;
+  int64_t r = r_arg;
+  if (r < 0) r = (int64_t)sched[(size_t)(step[0] - 1) * kSchedStride + 11] / refresh;
   const double eps = params[PB_EPS], beta = params[PB_BETA];
   double s = 0.0;
   for (int t = 0; t < p.T; ++t) {
@@ -55,52 +62,87 @@ __global__ __launch_bounds__(kScrBlock) void k_scr_sev(DevProblem p, const doubl
     s = fmax(s, zval[(size_t)t * p.Kp + k] - base);
   }
   sev[k] = s;
-  key[k] = splitmix_key(seed, r, k);
+  key[k] = splitmix_key(seed, (uint64_t)r, k);
 }
 
-__global__ __launch_bounds__(kScrBlock) void k_scr_top(const double* sev, int K, int n_top,
-                                                       double zeta, int* top) {
-  __shared__ double sv[kScrBlock];
-  const int k = blockIdx.x * kScrBlock + threadIdx.x;
+// Ranks by counting.  A block of 16 wavefronts owns 64 contingencies k (one
+// per lane); wavefront w compares them with the chunks of 64 j's w, w + 16,
+// ...: each lane loads one j of the chunk and the 64 values reach every lane
+// through readlane, so the inner loop runs on registers.  The 16 partial
+// counts are summed in LDS.
+__device__ __forceinline__ double bcast_f64(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ uint64_t bcast_u64(uint64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kRankWaves = kScrScan / 64;
+
+__global__ __launch_bounds__(kScrScan) void k_scr_top(const double* sev, int K, int n_top,
+                                                      double zeta, int* top) {
+  __shared__ int part[kRankWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
   const double my = k < K ? sev[k] : 0.0;
   int rank = 0;
-  for (int j0 = 0; j0 < K; j0 += kScrBlock) {
-    __syncthreads();
-    const int j = j0 + threadIdx.x;
-    sv[threadIdx.x] = j < K ? sev[j] : 0.0;
-    __syncthreads();
-    const int n = min(kScrBlock, K - j0);
-    for (int u = 0; u < n; ++u) {
-      const double v = sv[u];
+  for (int j0 = wv * 64; j0 < K; j0 += kRankWaves * 64) {
+    const int j = j0 + lane;
+    // past K: -inf, never above zeta, so it counts for nobody
+    const double vj = j < K ? sev[j] : -__builtin_inf();
+#pragma unroll 16
+    for (int u = 0; u < 64; ++u) {
+      const double v = bcast_f64(vj, u);
       rank += (v > zeta) && (v > my || (v == my && j0 + u < k));
     }
   }
-  if (k < K) top[k] = (my > zeta && rank < n_top) ? 1 : 0;
+  part[wv][lane] = rank;
+  __syncthreads();
+  if (wv == 0 && k < K) {
+    int r = 0;
+    for (int q = 0; q < kRankWaves; ++q) r += part[q][lane];
+    top[k] = (my > zeta && r < n_top) ? 1 : 0;
+  }
 }
 
-__global__ __launch_bounds__(kScrBlock) void k_scr_draw(const uint64_t* key, const int* top,
-                                                        int K, int n_act, int* sel) {
-  __shared__ uint64_t sk[kScrBlock];
-  __shared__ int st[kScrBlock];
-  const int k = blockIdx.x * kScrBlock + threadIdx.x;
+__global__ __launch_bounds__(kScrScan) void k_scr_draw(const uint64_t* key, const int* top,
+                                                       int K, int n_act, int* sel) {
+  __shared__ int part[kRankWaves][64];
+  __shared__ int ntops[kRankWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
   const uint64_t my = k < K ? key[k] : 0ull;
   const int mine = k < K ? top[k] : 0;
   int ntop = 0, rank = 0;
-  for (int j0 = 0; j0 < K; j0 += kScrBlock) {
-    __syncthreads();
-    const int j = j0 + threadIdx.x;
-    sk[threadIdx.x] = j < K ? key[j] : 0ull;
-    st[threadIdx.x] = j < K ? top[j] : 0;
-    __syncthreads();
-    const int n = min(kScrBlock, K - j0);
-    for (int u = 0; u < n; ++u) {
-      const int tj = st[u];
-      const uint64_t kj = sk[u];
-      ntop += tj;
-      rank += !tj && (kj < my || (kj == my && j0 + u < k));
+  for (int j0 = wv * 64; j0 < K; j0 += kRankWaves * 64) {
+    const int j = j0 + lane;
+    // past K: treated as worst-set members, which the draw skips
+    const int tj = j < K ? top[j] : 1;
+    const uint64_t kj = j < K ? key[j] : 0ull;
+    ntop += __popcll(__builtin_amdgcn_ballot_w64(j < K && tj != 0));
+#pragma unroll 16
+    for (int u = 0; u < 64; ++u) {
+      const int t = __builtin_amdgcn_readlane(tj, u);
+      const uint64_t kk = bcast_u64(kj, u);
+      rank += !t && (kk < my || (kk == my && j0 + u < k));
     }
   }
-  if (k < K) sel[k] = (mine || rank < n_act - ntop) ? 1 : 0;
+  part[wv][lane] = rank;
+  if (lane == 0) ntops[wv] = ntop;
+  __syncthreads();
+  if (wv == 0 && k < K) {
+    int r = 0, nt = 0;
+    for (int q = 0; q < kRankWaves; ++q) {
+      r += part[q][lane];
+      nt += ntops[q];
+    }
+    sel[k] = (mine || r < n_act - nt) ? 1 : 0;
+  }
 }
 
 __global__ __launch_bounds__(kScrScan) void k_scr_compact(const int* sel, int K, int Kp,
@@ -172,10 +214,12 @@ int launch_screen_select(const Problem* pr, const DevWork& w, int64_t round, voi
   const Screen& sc = pr->scr;
   const int K = pr->K, nb = (K + kScrBlock - 1) / kScrBlock;
   hipLaunchKernelGGL(k_scr_sev, dim3(nb), dim3(kScrBlock), 0, st, pr->dp, w.zval, w.params,
-                     sc.seed, (uint64_t)round, sc.sev, sc.key);
-  hipLaunchKernelGGL(k_scr_top, dim3(nb), dim3(kScrBlock), 0, st, sc.sev, K, sc.n_top, sc.zeta,
+                     (const double*)w.sched, (const int64_t*)w.step, (int64_t)sc.refresh, sc.seed,
+                     (int64_t)round, sc.sev, sc.key);
+  const int nr = (K + 63) / 64;
+  hipLaunchKernelGGL(k_scr_top, dim3(nr), dim3(kScrScan), 0, st, sc.sev, K, sc.n_top, sc.zeta,
                      sc.top);
-  hipLaunchKernelGGL(k_scr_draw, dim3(nb), dim3(kScrBlock), 0, st, sc.key, sc.top, K, sc.n_act,
+  hipLaunchKernelGGL(k_scr_draw, dim3(nr), dim3(kScrScan), 0, st, sc.key, sc.top, K, sc.n_act,
                      sc.sel);
   hipLaunchKernelGGL(k_scr_compact, dim3(1), dim3(kScrScan), 0, st, sc.sel, K, pr->Kp, sc.act_k,
                      sc.act_slot);

@@ -180,8 +180,8 @@ def test_refresh_selects_like_the_oracle(qg, name, top, rand, zeta_q, point):
         assert zero.sum() > K // 4
 
 
-def _solve_opts(qg, n, **kw):
-    return qg.solve_opts(n, [1e-3] * 6, n_total=20, eps0=1e-2, epsf=1e-3, beta0=0.5,
+def _solve_opts(qg, n, n_total=20, **kw):
+    return qg.solve_opts(n, [1e-3] * 6, n_total=n_total, eps0=1e-2, epsf=1e-3, beta0=0.5,
                          betaf=1.0, rho0=0.5, rhof=1.0, **kw)
 
 
@@ -233,6 +233,7 @@ def test_screened_solve_reports_the_exact_score(qg):
     x0 = synth.flat_start(c)
     xd, md, vd = prob.new_vector(x0), prob.new_vector(), prob.new_vector()
     rep = prob.solve(xd, md, vd, _solve_opts(qg, 20, use_graph=1))
+    assert rep.steps_done == 20
     torch.cuda.synchronize()
     ref = qg.Problem(c)
     t, _ = ref.eval_grad(xd, 0.0, 1.0, 1.0, grad=False)
@@ -266,3 +267,24 @@ def test_screening_argument_errors(qg):
         prob.solve(x, m, v, _solve_opts(qg, 2, profile=1))
     with pytest.raises(qg.QgError):
         qg.solve_batch([prob], [x], [m], [v], _solve_opts(qg, 2))
+
+
+def test_refresh_cycles_across_schedule_chunks(qg):
+    """Refresh every 7 steps while the schedule is uploaded in chunks of 10
+    (check_every): whole cycles replay as graphs, cycles cut by a chunk end
+    run as plain launches; states and sets equal a solve without graphs
+    bitwise."""
+    import torch
+    c = case("c2-sparse")
+    outs = []
+    for use_graph in (0, 1):
+        prob = qg.Problem(c)
+        prob.set_screening(0.1, 0.05, 0.0, 7, 11)
+        x0 = synth.flat_start(c)
+        xd, md, vd = prob.new_vector(x0), prob.new_vector(), prob.new_vector()
+        prob.solve(xd, md, vd, _solve_opts(qg, 30, n_total=30, check_every=10,
+                                           use_graph=use_graph))
+        torch.cuda.synchronize()
+        outs.append((xd.cpu().numpy(), md.cpu().numpy(), prob.active_contingencies()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
