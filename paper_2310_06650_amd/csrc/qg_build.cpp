@@ -297,8 +297,13 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   p->nb_bus = T * p->bus_chunks;
   p->nb_gen = (int)((int64_t(T) * G + kBlock - 1) / kBlock);
   {
+    // splits of the adjoint product's reduction: about one block per CU in
+    // all, each with at least kAdjStepsPerBlock MFMA k-steps when there are
+    // enough
     const int steps = p->Lp / 4;
-    p->nsplit = std::max(1, (steps + kAdjStepsPerBlock - 1) / kAdjStepsPerBlock);
+    const int nslab = (int)(round_up(G, 16) / 16);
+    const int most = std::max(1, (steps + kAdjStepsPerBlock - 1) / kAdjStepsPerBlock);
+    p->nsplit = std::min(most, std::max(1, (256 + nslab - 1) / nslab));
   }
   p->nKc = p->Kp / kCtgLanes;
   p->nLc = (p->Lp + kBlock - 1) / kBlock;

@@ -17,7 +17,7 @@ constexpr int kCtgLanes = 64;      // contingencies per wavefront in the map-red
 constexpr int kParams = 16;        // doubles in the per-step parameter block
 constexpr int kCtgMaxTc = 8;            // periods per block of the contingency kernel
 constexpr int kCtgLdsBytes = 64 * 1024; // LDS budget of one contingency block
-constexpr int kAdjStepsPerBlock = 64;   // MFMA k-steps per block of the adjoint product
+constexpr int kAdjStepsPerBlock = 32;   // MFMA k-steps per block of the adjoint product
 constexpr int kSchedCap = 2048;         // solve steps per uploaded schedule table
 constexpr int kSchedStride = 16;        // doubles per step in the schedule table
 

@@ -388,13 +388,11 @@ __device__ __forceinline__ void bus_segsum(const double* const (&src)[NV], const
 // [n0, n0+16) of C = A * B over the reduction range [k0, k1) (multiples of 4)
 // for all MT*16 rows; aload(k, row) supplies A[row][k] (zero outside A) and B
 // is row-major (ldb).  The range is split over the four wavefronts; operands
-// of 8 consecutive k-steps are loaded before their MFMAs so that their memory
-// latencies overlap.  The partial tiles are summed in LDS in wavefront order.
+// of NB consecutive k-steps are loaded before their MFMAs so that their
+// memory latencies overlap.  The partial tiles are summed in LDS in wavefront order.
 // v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; the result D[l/16 + 4r][l%16] sits in register r of lane l.
-constexpr int kSlabBatch = 8;
-
-template <int MT, class ALoad, class Epi>
+template <int MT, int NB, class ALoad, class Epi>
 __device__ __forceinline__ void mfma_slab(ALoad aload, const double* __restrict__ B, int ldb,
                                           int k0, int k1, int n0, double* lds, Epi epi) {
   const int tid = threadIdx.x;
@@ -407,27 +405,39 @@ __device__ __forceinline__ void mfma_slab(ALoad aload, const double* __restrict_
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
   const int kr = lane >> 4, cc = lane & 15;
   int st = s0;
-  for (; st + kSlabBatch <= s1; st += kSlabBatch) {
-    double bb[kSlabBatch], aa[kSlabBatch][MT];
+  for (; st + NB <= s1; st += NB) {
+    double bb[NB], aa[NB][MT];
 #pragma unroll
-    for (int u = 0; u < kSlabBatch; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int k = k0 + (st + u) * 4 + kr;
       bb[u] = B[(size_t)k * ldb + n0 + cc];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) aa[u][mt] = aload(k, mt * 16 + cc);
     }
 #pragma unroll
-    for (int u = 0; u < kSlabBatch; ++u)
+    for (int u = 0; u < NB; ++u)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
         acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[u][mt], bb[u], acc[mt], 0, 0, 0);
   }
-  for (; st < s1; ++st) {
-    const int k = k0 + st * 4 + kr;
-    const double b = B[(size_t)k * ldb + n0 + cc];
+  if (st < s1) {
+    // the last, partial batch: its loads in flight together as well (the
+    // step range is wavefront-uniform, so the guards do not diverge)
+    double bb[NB], aa[NB][MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aload(k, mt * 16 + cc), b, acc[mt], 0, 0, 0);
+    for (int u = 0; u < NB; ++u) {
+      const bool in = st + u < s1;
+      const int k = k0 + (st + u) * 4 + kr;
+      bb[u] = in ? B[(size_t)k * ldb + n0 + cc] : 0.0;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) aa[u][mt] = in ? aload(k, mt * 16 + cc) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (st + u < s1)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[u][mt], bb[u], acc[mt], 0, 0, 0);
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -446,15 +456,18 @@ __device__ __forceinline__ void mfma_slab(ALoad aload, const double* __restrict_
   __syncthreads();
 }
 
-template <class ALoad, class Epi>
+// NB: k-steps whose operands are loaded together; more steps in flight
+// cost registers (the flow product shares its kernel with the branch and
+// period blocks, so it takes 4 with 3-4 row tiles).
+template <int NB34, class ALoad, class Epi>
 __device__ __forceinline__ void mfma_slab_dispatch(int mtiles, ALoad aload, const double* B,
                                                    int ldb, int k0, int k1, int n0, double* lds,
                                                    Epi epi) {
   switch (mtiles) {
-    case 1: mfma_slab<1>(aload, B, ldb, k0, k1, n0, lds, epi); break;
-    case 2: mfma_slab<2>(aload, B, ldb, k0, k1, n0, lds, epi); break;
-    case 3: mfma_slab<3>(aload, B, ldb, k0, k1, n0, lds, epi); break;
-    default: mfma_slab<4>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    case 1: mfma_slab<1, 8>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    case 2: mfma_slab<2, 8>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    case 3: mfma_slab<3, NB34>(aload, B, ldb, k0, k1, n0, lds, epi); break;
+    default: mfma_slab<4, NB34>(aload, B, ldb, k0, k1, n0, lds, epi); break;
   }
 }
 
@@ -551,12 +564,36 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
   double acc[3] = {0.0, 0.0, 0.0};  // dev, pen, sum r
   for (int j = tid; j < G; j += kBlock) {
     const size_t e = (size_t)t * G + j;
+    // every load of the generator first, so that their latencies overlap
     const double pj = xP[e], qj = xQ[e], rj = xR[e], uj = xU[e];
     const double pm1 = t > 0 ? xP[e - G] : p.p0[j];
     const double um1 = t > 0 ? xU[e - G] : p.u0[j];
+    const bool nxt = t + 1 < T;
+    const double p1 = nxt ? xP[e + G] : 0.0, u1 = nxt ? xU[e + G] : 0.0;
+    const double pmax = p.pmax[j], pmin = p.pmin[j], qmax = p.qmax[j], qmin = p.qmin[j];
+    const double rmax = p.rmax[j], ru = p.ru[j], rd = p.rd[j], rusu = p.rusu[j];
+    const double rdsd = p.rdsd[j], con = p.con[j], csu = p.csu[j], csd = p.csd[j];
+    const double cr = p.cr[j];
+    double sz4[4], cm4[4], pc4[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bool in = m < M;
+      sz4[m] = in ? p.seg_size[j * M + m] : 0.0;
+      cm4[m] = in ? p.seg_cost[j * M + m] : 0.0;
+      pc4[m] = in ? p.pcum[j * M + m] : 0.0;
+    }
     // block-bid energy cost, eq. (costs): sum_m c_m max(min(p - Pcum_{m-1}, D_m), 0)
     double cost = 0.0, dcost = 0.0, lo = 0.0;
-    for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (m < M) {
+        const double am = pj - lo;
+        cost += cm4[m] * fmax(fmin(am, sz4[m]), 0.0);
+        if (am > 0.0 && am <= sz4[m]) dcost += cm4[m];
+        lo = pc4[m];
+      }
+    }
+    for (int m = 4; m < M; ++m) {
       const double am = pj - lo;
       const double sz = p.seg_size[j * M + m], cm = p.seg_cost[j * M + m];
       cost += cm * fmax(fmin(am, sz), 0.0);
@@ -564,45 +601,44 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
       lo = p.pcum[j * M + m];
     }
     const double du = uj - um1;
-    const double dev = dtt * cost + dtt * p.con[j] * uj + p.csu[j] * fmax(du, 0.0) +
-                       p.csd[j] * fmax(-du, 0.0) + dtt * p.cr[j] * rj;
+    const double dev = dtt * cost + dtt * con * uj + csu * fmax(du, 0.0) +
+                       csd * fmax(-du, 0.0) + dtt * cr * rj;
     double gp = dtt * dcost;
-    double gu = dtt * p.con[j] + (du > 0.0 ? p.csu[j] : 0.0) - (-du > 0.0 ? p.csd[j] : 0.0);
-    double gr = dtt * p.cr[j];
+    double gu = dtt * con + (du > 0.0 ? csu : 0.0) - (-du > 0.0 ? csd : 0.0);
+    double gr = dtt * cr;
     double gq = 0.0;
-    if (t + 1 < T) {
-      const double du1 = xU[e + G] - uj;
-      gu -= (du1 > 0.0 ? p.csu[j] : 0.0) - (-du1 > 0.0 ? p.csd[j] : 0.0);
+    if (nxt) {
+      const double du1 = u1 - uj;
+      gu -= (du1 > 0.0 ? csu : 0.0) - (-du1 > 0.0 ? csd : 0.0);
     }
     double pen = 0.0, a_, dd;
-    a_ = pj + rj - p.pmax[j] * uj;                        // headroom
+    a_ = pj + rj - pmax * uj;                             // headroom
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gp += dd; gr += dd; gu -= dd * p.pmax[j];
-    a_ = p.pmin[j] * uj - pj;                             // minimum output
+    gp += dd; gr += dd; gu -= dd * pmax;
+    a_ = pmin * uj - pj;                                  // minimum output
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gu += dd * p.pmin[j]; gp -= dd;
-    a_ = pj - pm1 - dtt * (p.ru[j] * uj + p.rusu[j] * (1.0 - uj));   // ramp up
+    gu += dd * pmin; gp -= dd;
+    a_ = pj - pm1 - dtt * (ru * uj + rusu * (1.0 - uj));  // ramp up
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gp += dd; gu -= dd * dtt * (p.ru[j] - p.rusu[j]);
-    a_ = pm1 - pj - dtt * (p.rd[j] * uj + p.rdsd[j] * (1.0 - uj));   // ramp down
+    gp += dd; gu -= dd * dtt * (ru - rusu);
+    a_ = pm1 - pj - dtt * (rd * uj + rdsd * (1.0 - uj));  // ramp down
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gp -= dd; gu -= dd * dtt * (p.rd[j] - p.rdsd[j]);
-    a_ = qj - p.qmax[j] * uj;                             // reactive upper
+    gp -= dd; gu -= dd * dtt * (rd - rdsd);
+    a_ = qj - qmax * uj;                                  // reactive upper
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gq += dd; gu -= dd * p.qmax[j];
-    a_ = p.qmin[j] * uj - qj;                             // reactive lower
+    gq += dd; gu -= dd * qmax;
+    a_ = qmin * uj - qj;                                  // reactive lower
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gu += dd * p.qmin[j]; gq -= dd;
-    a_ = rj - p.rmax[j] * uj;                             // reserve capability
+    gu += dd * qmin; gq -= dd;
+    a_ = rj - rmax * uj;                                  // reserve capability
     pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
-    gr += dd; gu -= dd * p.rmax[j];
-    if (t + 1 < T) {  // the next period's ramp constraints depend on p_t
+    gr += dd; gu -= dd * rmax;
+    if (nxt) {  // the next period's ramp constraints depend on p_t
       const double dt1 = p.dt[t + 1];
       const double k1 = sp.rho_s * p.rho * sp.beta * dt1;
-      const double p1 = xP[e + G], u1 = xU[e + G];
-      a_ = p1 - pj - dt1 * (p.ru[j] * u1 + p.rusu[j] * (1.0 - u1));
+      a_ = p1 - pj - dt1 * (ru * u1 + rusu * (1.0 - u1));
       gp -= k1 * soft_relu_d(a_, eps);
-      a_ = pj - p1 - dt1 * (p.rd[j] * u1 + p.rdsd[j] * (1.0 - u1));
+      a_ = pj - p1 - dt1 * (rd * u1 + rdsd * (1.0 - u1));
       gp += k1 * soft_relu_d(a_, eps);
     }
     w.gdev[0 * TG + e] = gp;
@@ -657,7 +693,7 @@ __device__ void flow_slab(const EvalArgs& a, int slab, double* smem) {
       if (k >= 0) Fk[(size_t)row * Kp + k] = f;
     }
   };
-  mfma_slab_dispatch(p.Tp / 16, aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
+  mfma_slab_dispatch<4>(p.Tp / 16, aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
 }
 
 // Blocks [0, nb_br): branch forward; [nb_br, nb_br + T): one period each;
@@ -919,12 +955,8 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   // independent loads first
   double r = 0.0, q = 0.0, Fl = 0.0, q2l = 0.0, sm2 = 0.0, sm = 0.0;
   int kk = -1;
+  const size_t o = (size_t)t * Lp + l;
   if (hasl) {
-    const size_t o = (size_t)t * Lp + l;
-    if (K > 0) {  // without contingencies the partials were never written
-      r = strided_sum<16>(w.rpart + o, a.nKb, (size_t)T * Lp);
-      q = strided_sum<16>(w.qpart + o, a.nKb, (size_t)T * Lp);
-    }
     Fl = w.F[o];
     q2l = w.q2[o];
     sm2 = p.ctg_smax2[l];
@@ -933,45 +965,64 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   }
   double sacc[1] = {0.0};
   if (K > 0) {
-    // worst contingency of the period from the per-chunk partials (chunk
-    // order), 16 chunks' loads in flight at a time
+    // per-chunk worst penalties and sums: chunk c0 + u in lane u (vector
+    // loads, issued first), combined by wavefront reductions (the argmax is
+    // a total order, the sum has a fixed order); then the k-block partials
+    // of R and Q in k-block order, 16 of each in flight together.  Without
+    // contingencies the partials were never written.
+    const int lane = tid & 63;
     double zmax = -DBL_MAX, zsum = 0.0;
     int kstar = INT_MAX;
     const size_t ob = (size_t)t * a.nKc;
-    for (int c0 = 0; c0 < a.nKc; c0 += 16) {
-      double vz[16], vi[16], vs[16];
+    double cz = -DBL_MAX, cs = 0.0;
+    int ci = INT_MAX;
+    if (lane < a.nKc) {
+      cz = w.zmaxp[ob + lane];
+      ci = (int)w.zargp[ob + lane];
+      cs = w.zsump[ob + lane];
+    }
+    const size_t st = (size_t)T * Lp;
+    for (int c0 = 0; c0 < a.nKb; c0 += 16) {
+      double vr[16], vq[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const bool in = c0 + u < a.nKc;
-        vz[u] = in ? w.zmaxp[ob + c0 + u] : -DBL_MAX;
-        vi[u] = in ? w.zargp[ob + c0 + u] : (double)INT_MAX;
-        vs[u] = in ? w.zsump[ob + c0 + u] : 0.0;
+        const bool ib = hasl && c0 + u < a.nKb;
+        vr[u] = ib ? w.rpart[o + (size_t)(c0 + u) * st] : 0.0;
+        vq[u] = ib ? w.qpart[o + (size_t)(c0 + u) * st] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        if (c0 + u < a.nKc) {
-          const int i = (int)vi[u];
-          if (better(vz[u], i, zmax, kstar)) { zmax = vz[u]; kstar = i; }
-          zsum += vs[u];
-        }
+        r += vr[u];
+        q += vq[u];
       }
+    }
+    for (int c0 = 0; c0 < a.nKc; c0 += 64) {
+      if (c0 > 0) {
+        const int c = c0 + lane;
+        cz = c < a.nKc ? w.zmaxp[ob + c] : -DBL_MAX;
+        ci = c < a.nKc ? (int)w.zargp[ob + c] : INT_MAX;
+        cs = c < a.nKc ? w.zsump[ob + c] : 0.0;
+      }
+      wave_argmax(cz, ci);
+      const double ssum = wave_sum(cs);
+      if (better(cz, ci, zmax, kstar)) { zmax = cz; kstar = ci; }
+      zsum += ssum;
     }
     if (!(kstar >= 0 && kstar < K)) kstar = 0;  // NaN penalties: keep every index in range
     const double invK = 1.0 / (double)K;
     if (hasl) {
       r *= invK;
       q *= invK;
-      if (l != p.brk[kstar]) {
-        const double lo = lodf_value(p, l, kstar);
-        const double P = fma(lo, w.Fk[(size_t)t * Kp + kstar], Fl);
-        const double s2 = fma(P, P, q2l);
-        if (s2 > sm2) {
-          double dP, dq;
-          ctg_overload(P, s2, sm, eps, eps * eps, kt, dP, dq);
-          r += dP;
-          q += dq;
-          sacc[0] = lo * dP;
-        }
+      // the outaged branch's own factor is NaN: it never tests overloaded
+      const double lo = lodf_value(p, l, kstar);
+      const double P = fma(lo, w.Fk[(size_t)t * Kp + kstar], Fl);
+      const double s2 = fma(P, P, q2l);
+      if (s2 > sm2) {
+        double dP, dq;
+        ctg_overload(P, s2, sm, eps, eps * eps, kt, dP, dq);
+        r += dP;
+        q += dq;
+        sacc[0] = lo * dP;
       }
       if (kk >= 0) {
         const int sl = a.act_slot ? a.act_slot[kk] : kk;
@@ -993,8 +1044,6 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   if (l < Lp) {
     w.gfT[(size_t)l * Tp + t] = hasl ? r : 0.0;
     w.qtot[(size_t)t * Lp + l] = hasl ? q : 0.0;
-    if (t == 0)
-      for (int cc = T; cc < Tp; ++cc) w.gfT[(size_t)l * Tp + cc] = 0.0;
   }
   block_sum<1>(sacc, red);
   if (tid == 0) w.smaxp[(size_t)t * a.nLc + lc] = sacc[0];
@@ -1065,11 +1114,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
     const int T = p.T, Tp = p.Tp, G16 = p.G16;
     double* out = a.w.gpdc + (size_t)sp * T * G16;
     const double* gfT = a.w.gfT;
-    auto aload = [=](int k, int row) -> double { return gfT[(size_t)k * Tp + row]; };
+    // rows past T of gfT are never written: they enter as zeros
+    auto aload = [=](int k, int row) -> double {
+      return row < T ? gfT[(size_t)k * Tp + row] : 0.0;
+    };
     auto epi = [=](int row, int col, double v) {
       if (row < T) out[(size_t)row * G16 + col] = v;
     };
-    mfma_slab_dispatch(p.Tp / 16, aload, p.isf_ga, G16, k0, k1, n0, smem, epi);
+    mfma_slab_dispatch<8>(p.Tp / 16, aload, p.isf_ga, G16, k0, k1, n0, smem, epi);
     return;
   }
   branch_reverse(a, blockIdx.x - nslab * a.nsplit);
