@@ -171,7 +171,9 @@ WorkLayout work_layout(const Problem& p) {
       T * (size_t)p.nKc * D, T * (size_t)p.nKc * D,     // zmaxp, zargp
       T * (size_t)p.nKc * D,                            // zsump
       T * D,                                            // kstar
-      T * (size_t)p.nLc * D};                           // smaxp
+      T * (size_t)p.nLc * D,                            // smaxp
+      T * G * D, T * G * D,                             // lamg, lamqg
+      T * (size_t)p.G16 * D};                           // isfk
   WorkLayout w;
   const int n = (int)(sizeof(cnt) / sizeof(cnt[0]));
   size_t o = 0;
@@ -189,11 +191,11 @@ WorkLayout work_layout(const Problem& p) {
 int default_ctg_tc(const Problem& p, int wl) {
   // periods per block of the contingency map-reduce.  Short chunks give the
   // chip more blocks and shorter per-block tails, but every chunk re-reads
-  // the outage factors: take 2 periods while the re-reads stay within a
+  // the outage factors: take 4 periods while the re-reads stay within a
   // 64 MB budget per step, else the longest chunk (8 periods).
   const double lodf_bytes = (double)p.Lp * p.Kp * lodf_elem_bytes(lodf_kind_of(p.flags));
-  const int chunks2 = (p.T + 1) / 2;
-  int tc = (lodf_bytes * chunks2 <= 64.0 * (1 << 20)) ? 2 : kCtgMaxTc;
+  const int chunks4 = (p.T + 3) / 4;
+  int tc = (lodf_bytes * chunks4 <= 64.0 * (1 << 20)) ? 4 : kCtgMaxTc;
   tc = std::min(tc, ctg_tc_cap(wl));
   return std::max(1, std::min(tc, p.T));
 }
@@ -692,6 +694,7 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   w.epGV = D(21); w.epGT = D(22); w.tpart = D(23); w.terms = D(24);
   w.drs = D(25); w.zmaxp = D(26); w.zargp = D(27); w.zsump = D(28); w.kstar = D(29);
   w.smaxp = D(30);
+  w.lamg = D(31); w.lamqg = D(32); w.isfk = D(33);
   return w;
 }
 

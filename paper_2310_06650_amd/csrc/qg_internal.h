@@ -104,6 +104,8 @@ struct DevWork {
   double* zsump;       // [T][nKc]  per-chunk penalty sum
   double* kstar;       // [T]       worst contingency of the period
   double* smaxp;       // [T][nLc]  per-chunk dL/dF of the worst contingency's own branch
+  double* lamg; double* lamqg;   // [T][G] balance multipliers at each generator's bus
+  double* isfk;        // [T][G16]  ISF[br(k*_t)][bus(j)] - rowsum/N of the period's worst outage
 };
 
 // Offsets of the term partial sums inside DevWork::tpart.

@@ -750,8 +750,15 @@ __device__ void bus_balance(const EvalArgs& a, int blk, double* smem) {
     const double dp = p.load_p[ti] + fl[0] - sp_;
     const double dq = p.load_q[ti] + fl[1] - sq;
     const double kb = p.dt[t] * beta;
-    w.lamp[ti] = kb * p.c_p * soft_abs_d(dp, eps);
-    w.lamq[ti] = kb * p.c_q * soft_abs_d(dq, eps);
+    const double lp = kb * p.c_p * soft_abs_d(dp, eps), lq = kb * p.c_q * soft_abs_d(dq, eps);
+    w.lamp[ti] = lp;
+    w.lamq[ti] = lq;
+    // the same multipliers per generator of the bus (read by k_final)
+    for (int g = p.gptr[i]; g < p.gptr[i + 1]; ++g) {
+      const size_t e = (size_t)t * p.G + p.glist[g];
+      w.lamg[e] = lp;
+      w.lamqg[e] = lq;
+    }
     part[0] = kb * (p.c_p * sqrt(dp * dp + eps * eps) + p.c_q * sqrt(dq * dq + eps * eps));
   }
   block_sum<1>(part, smem);
@@ -1100,7 +1107,8 @@ __device__ void branch_reverse(const EvalArgs& a, int blk) {
 }
 
 // Blocks [0, nslab * nsplit): the DC part of dL/dp, one 16-generator slab and
-// one slice of the branch dimension each (partials summed in k_final).
+// one slice of the branch dimension each (partials summed in k_final); then
+// nb_br branch-reverse blocks; then the worst outage's ISF rows.
 __global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
   __shared__ double smem[kSlabLds];
   const DevProblem& p = a.p;
@@ -1124,7 +1132,19 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
     mfma_slab_dispatch<8>(p.Tp / 16, aload, p.isf_ga, G16, k0, k1, n0, smem, epi);
     return;
   }
-  branch_reverse(a, blockIdx.x - nslab * a.nsplit);
+  const int b = blockIdx.x - nslab * a.nsplit;
+  if (b < a.nb_br) {
+    branch_reverse(a, b);
+    return;
+  }
+  // the worst outage's ISF row of each period (generator columns), for the
+  // rank-1 outage-correction term that k_final adds to dL/dp
+  const int idx = (b - a.nb_br) * kBlock + threadIdx.x;
+  if (idx < p.T * p.G16) {
+    const int t = idx / p.G16, j = idx - t * p.G16;
+    const int bks = p.brk[(int)a.w.kstar[t]];
+    a.w.isfk[idx] = p.isf_ga[(size_t)bks * p.G16 + j];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1135,18 +1155,33 @@ struct AdamCtx {
   int eps_num;
 };
 
-__device__ __forceinline__ void adam_entry(double* x, double* m, double* v, size_t e, double g,
-                                           double lr, double lo, double hi, const AdamCtx& c) {
-  const double mm = c.b1 * m[e] + (1.0 - c.b1) * g;
-  const double vv = c.b2 * v[e] + (1.0 - c.b2) * g * g;
-  m[e] = mm;
-  v[e] = vv;
+// x, m, v of one variable.  The loads of every variable a thread updates are
+// issued before its first store: x, m and v may alias as far as the compiler
+// knows, so a load after a store would wait for it.
+struct AdamVar {
+  double x, m, v;
+};
+__device__ __forceinline__ AdamVar adam_load(const double* x, const double* m, const double* v,
+                                             size_t e) {
+  return AdamVar{x[e], m[e], v[e]};
+}
+__device__ __forceinline__ void adam_store(double* x, double* m, double* v, size_t e,
+                                           const AdamVar& s, double g, double lr, double lo,
+                                           double hi, const AdamCtx& c) {
+  const double mm = c.b1 * s.m + (1.0 - c.b1) * g;
+  const double vv = c.b2 * s.v + (1.0 - c.b2) * g * g;
   const double mh = mm / c.bc1;
   const double vh = vv / c.bc2;
   const double num = c.eps_num ? mh + c.eps : mh;
-  double xn = x[e] - lr * num / (sqrt(vh) + c.eps);
+  double xn = s.x - lr * num / (sqrt(vh) + c.eps);
   xn = fmin(fmax(xn, lo), hi);
+  m[e] = mm;
+  v[e] = vv;
   x[e] = xn;
+}
+__device__ __forceinline__ void adam_entry(double* x, double* m, double* v, size_t e, double g,
+                                           double lr, double lo, double hi, const AdamCtx& c) {
+  adam_store(x, m, v, e, adam_load(x, m, v, e), g, lr, lo, hi, c);
 }
 
 __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
@@ -1170,14 +1205,19 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     const int i0 = c * kBlock;
     const int nbus = min(kBlock, N - i0);
     const double* src[2] = {w.epGV + (size_t)t * p.twoL, w.epGT + (size_t)t * p.twoL};
+    // the bus's Adam state, loaded while the endpoint sums are formed
+    const int i = i0 + tid;
+    const size_t ev = (size_t)t * N + i, et = (size_t)T * N + ev;
+    const bool upd = a.fuse_adam && tid < nbus;
+    const AdamVar sv = upd ? adam_load(xm, a.m, a.v, ev) : AdamVar{0.0, 0.0, 0.0};
+    const AdamVar st = upd ? adam_load(xm, a.m, a.v, et) : AdamVar{0.0, 0.0, 0.0};
+    const double vlo = upd ? p.vmin[i] : 0.0, vhi = upd ? p.vmax[i] : 0.0;
     double gsum[2];
     bus_segsum<2>(src, p.bptr, i0, nbus, smem, gsum);
     if (tid < nbus) {
-      const int i = i0 + tid;
-      const size_t ev = (size_t)t * N + i, et = (size_t)T * N + ev;
       if (a.fuse_adam) {
-        adam_entry(xm, a.m, a.v, ev, gsum[0], alpha[QG_C_V], p.vmin[i], p.vmax[i], ac);
-        adam_entry(xm, a.m, a.v, et, gsum[1], alpha[QG_C_TH], -DBL_MAX, DBL_MAX, ac);
+        adam_store(xm, a.m, a.v, ev, sv, gsum[0], alpha[QG_C_V], vlo, vhi, ac);
+        adam_store(xm, a.m, a.v, et, st, gsum[1], alpha[QG_C_TH], -DBL_MAX, DBL_MAX, ac);
       } else if (a.grad) {
         a.grad[ev] = gsum[0];
         a.grad[et] = gsum[1];
@@ -1193,23 +1233,32 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     const int idx = gb * kBlock + tid;
     if (idx >= T * G) return;
     const int t = idx / G, j = idx - t * G;
-    const double smax = strided_sum<16>(w.smaxp + (size_t)t * a.nLc, a.nLc, 1);
-    const int bks = p.brk[(int)w.kstar[t]];
-    double dc = smax * p.isf_ga[(size_t)bks * p.G16 + j];
-    dc += strided_sum<16>(w.gpdc + (size_t)t * p.G16 + j, a.nsplit, (size_t)T * p.G16);
     const size_t TG = (size_t)T * G;
     const size_t base = 2 * (size_t)T * N;
     const size_t e = (size_t)t * G + j;
-    const size_t tb = (size_t)t * N + p.gen_bus[j];
-    const double gp = w.gdev[e] - w.lamp[tb] + dc;
-    const double gq = w.gdev[TG + e] - w.lamq[tb];
-    const double gr = w.gdev[2 * TG + e] - w.drs[t];
-    const double gu = w.gdev[3 * TG + e];
+    // every single load first (the Adam state of the four variables too),
+    // then the partial sums
+    AdamVar s4[4];
+    if (a.fuse_adam)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s4[q] = adam_load(xm, a.m, a.v, base + q * TG + e);
+    const double gd0 = w.gdev[e], gd1 = w.gdev[TG + e], gd2 = w.gdev[2 * TG + e];
+    const double gd3 = w.gdev[3 * TG + e];
+    const double lg = w.lamg[e], lqg = w.lamqg[e], drs = w.drs[t];
+    const double isk = w.isfk[(size_t)t * p.G16 + j];
+    const double pmax = p.pmax[j], qmin = p.qmin[j], qmax = p.qmax[j], rmax = p.rmax[j];
+    const double smax = strided_sum<16>(w.smaxp + (size_t)t * a.nLc, a.nLc, 1);
+    double dc = smax * isk;
+    dc += strided_sum<16>(w.gpdc + (size_t)t * p.G16 + j, a.nsplit, (size_t)T * p.G16);
+    const double gp = gd0 - lg + dc;
+    const double gq = gd1 - lqg;
+    const double gr = gd2 - drs;
+    const double gu = gd3;
     if (a.fuse_adam) {
-      adam_entry(xm, a.m, a.v, base + e, gp, alpha[QG_C_P], 0.0, p.pmax[j], ac);
-      adam_entry(xm, a.m, a.v, base + TG + e, gq, alpha[QG_C_Q], p.qmin[j], p.qmax[j], ac);
-      adam_entry(xm, a.m, a.v, base + 2 * TG + e, gr, alpha[QG_C_R], 0.0, p.rmax[j], ac);
-      adam_entry(xm, a.m, a.v, base + 3 * TG + e, gu, alpha[QG_C_U], 0.0, 1.0, ac);
+      adam_store(xm, a.m, a.v, base + e, s4[0], gp, alpha[QG_C_P], 0.0, pmax, ac);
+      adam_store(xm, a.m, a.v, base + TG + e, s4[1], gq, alpha[QG_C_Q], qmin, qmax, ac);
+      adam_store(xm, a.m, a.v, base + 2 * TG + e, s4[2], gr, alpha[QG_C_R], 0.0, rmax, ac);
+      adam_store(xm, a.m, a.v, base + 3 * TG + e, s4[3], gu, alpha[QG_C_U], 0.0, 1.0, ac);
     } else if (a.grad) {
       a.grad[base + e] = gp;
       a.grad[base + TG + e] = gq;
@@ -1218,18 +1267,20 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     }
     return;
   }
-  // terms: deterministic sums of the partials
+  // terms: deterministic sums of the partials (one pass, so that all of a
+  // thread's loads are in flight together)
   const TermOffsets& to = a.toff;
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int q = tid; q < a.nb_br; q += kBlock) { v[2] += w.tpart[to.br + q]; v[3] += w.tpart[to.ang + q]; }
-  for (int q = tid; q < T; q += kBlock) {
-    v[0] += w.tpart[to.dev + q];
-    v[4] += w.tpart[to.pen + q];
-    v[5] += w.tpart[to.rsv + q];
-    v[6] += w.tpart[to.cmax + q];
-    v[7] += w.tpart[to.cmean + q];
+  const int nq = max(max(a.nb_br, T), a.nb_bus);
+  for (int q = tid; q < nq; q += kBlock) {
+    const bool ib = q < a.nb_br, it = q < T, iu = q < a.nb_bus;
+    const double br = ib ? w.tpart[to.br + q] : 0.0, an = ib ? w.tpart[to.ang + q] : 0.0;
+    const double dv = it ? w.tpart[to.dev + q] : 0.0, pn = it ? w.tpart[to.pen + q] : 0.0;
+    const double rs = it ? w.tpart[to.rsv + q] : 0.0, cx = it ? w.tpart[to.cmax + q] : 0.0;
+    const double cm = it ? w.tpart[to.cmean + q] : 0.0, bl = iu ? w.tpart[to.bal + q] : 0.0;
+    v[0] += dv; v[1] += bl; v[2] += br; v[3] += an;
+    v[4] += pn; v[5] += rs; v[6] += cx; v[7] += cm;
   }
-  for (int q = tid; q < a.nb_bus; q += kBlock) v[1] += w.tpart[to.bal + q];
   block_sum<8>(v, smem);
   if (tid == 0) {
     double out[QG_NTERMS];
@@ -1373,7 +1424,10 @@ static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStr
       hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0, s, a);
       break;
     case 4:
-      hipLaunchKernelGGL(k_adjoint, dim3(pr->G16 / 16 * pr->nsplit + pr->nb_br), dim3(kBlock), 0,
+      hipLaunchKernelGGL(k_adjoint,
+                         dim3(pr->G16 / 16 * pr->nsplit + pr->nb_br +
+                              (pr->T * pr->G16 + kBlock - 1) / kBlock),
+                         dim3(kBlock), 0,
                          s, a);
       break;
     default:
