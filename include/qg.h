@@ -285,7 +285,8 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
  * (Lp = L rounded up to 64, Kp = K up to 64, G16 = G up to 16, G4 = G up to 4,
  * Tp = T up to 16; nLb, nKb = partial-sum counts of the contingency
  * map-reduce; ctg_bl, ctg_wl, ctg_tc = its tile).  With capacity >= 17,
- * dims[16] = storage of the outage factors (0 FP64, 1 FP32, 2 BF16).
+ * dims[16] = storage of the outage factors (0 FP64, 1 FP32, 2 BF16); with
+ * capacity >= 18, dims[17] = branch tiles per block (qg_set_ctg_ltiles).
  * capacity must be >= 16.
  */
 qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacity);
@@ -299,6 +300,17 @@ qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacit
  * a change.  Errors: ARG.
  */
 qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
+
+/*
+ * Branch tiles (of wl * bl branches) that one block of the contingency
+ * map-reduce covers, lt in [1, 64], or 0 for the default (doubling from 1
+ * while at least 2048 blocks remain).  More tiles per block spread each
+ * block's fixed costs and shrink the per-(period, contingency) partial sums;
+ * fewer leave more blocks.  qg_set_ctg_tile resets it to the default.
+ * Results depend on it only through the order of floating-point sums.  A
+ * step graph cached by qg_solve is re-captured after a change.  Errors: ARG.
+ */
+qg_status qg_set_ctg_ltiles(qg_problem* prob, int32_t lt);
 
 /*
  * Test support: copy an intermediate array of the last evaluation from the

@@ -190,10 +190,10 @@ qg_status qg_problem_dims(const qg_problem* pr, int32_t* d, int32_t capacity) {
   if (s != QG_OK) return s;
   if (!d || capacity < 16) return fail(QG_ERR_ARG, "dims needs 16 entries");
   const qg::Problem& p = pr->p;
-  const int32_t v[17] = {p.N,  p.L,   p.G,   p.T,       p.M,       p.K,       p.Lp,
+  const int32_t v[18] = {p.N,  p.L,   p.G,   p.T,       p.M,       p.K,       p.Lp,
                          p.Kp, p.G16, p.G4,  p.Tp,      p.nLb,     p.nKb,     p.tile.bl,
-                         p.tile.wl,   p.tile.tc, p.dp.lodf_kind};
-  std::memcpy(d, v, sizeof(int32_t) * (capacity >= 17 ? 17 : 16));
+                         p.tile.wl,   p.tile.tc, p.dp.lodf_kind, p.tile.lt};
+  std::memcpy(d, v, sizeof(int32_t) * (capacity >= 18 ? 18 : capacity >= 17 ? 17 : 16));
   return QG_OK;
 }
 
@@ -328,14 +328,25 @@ qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl, int32_t tc) {
       bl * wl < 16)
     return fail(QG_ERR_ARG, "tile must have bl in {8,16,32}, wl in {1,2,4,8}, bl*wl >= 16");
   qg::Problem& p = pr->p;
-  const int span = bl * wl;
   if (tc <= 0) tc = qg::default_ctg_tc(p, wl);
   if (tc > p.T) tc = p.T;
   if (tc > qg::kCtgMaxTc) return fail(QG_ERR_ARG, "at most 8 periods per block");
   if (tc > qg::ctg_tc_cap(wl))
     return fail(QG_ERR_ARG, "too many periods per block for the LDS budget at this wl");
-  p.tile = qg::CtgTile{bl, wl, tc};
-  p.nLb = (p.Lp + span - 1) / span;
+  qg::CtgTile t{bl, wl, tc, 1};
+  t.lt = qg::default_ctg_lt(p, t);
+  qg::apply_ctg_tile(&p, t);
+  return QG_OK;
+}
+
+qg_status qg_set_ctg_ltiles(qg_problem* pr, int32_t lt) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (lt < 0 || lt > 64) return fail(QG_ERR_ARG, "lt must lie in [0, 64]");
+  qg::Problem& p = pr->p;
+  qg::CtgTile t = p.tile;
+  t.lt = lt > 0 ? lt : qg::default_ctg_lt(p, t);
+  qg::apply_ctg_tile(&p, t);
   return QG_OK;
 }
 
@@ -560,7 +571,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     if (hit && std::memcmp(&pr->p.graph_mode, &sm_run, sizeof(sm_run)) != 0) hit = false;
     // and so is the contingency tile (grid and LDS size of the map-reduce)
     const qg::CtgTile& gt = pr->p.graph_tile;
-    if (hit && (gt.bl != p.tile.bl || gt.wl != p.tile.wl || gt.tc != p.tile.tc)) hit = false;
+    if (hit && (gt.bl != p.tile.bl || gt.wl != p.tile.wl || gt.tc != p.tile.tc ||
+                gt.lt != p.tile.lt))
+      hit = false;
     if (!hit) {
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; pr->p.graph_exec = nullptr; }
       hipGraph_t g;

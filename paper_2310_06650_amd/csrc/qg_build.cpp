@@ -200,6 +200,28 @@ int default_ctg_tc(const Problem& p, int wl) {
   return std::max(1, std::min(tc, p.T));
 }
 
+int default_ctg_lt(const Problem& p, const CtgTile& t) {
+  // branch tiles per block: more tiles per block amortise the block's
+  // prologue and epilogue and divide the (t, k) partial sums of z and S,
+  // while at least 2048 blocks remain to fill the chip
+  const int span = t.bl * t.wl;
+  const int nl1 = (p.Lp + span - 1) / span;
+  const int ntc = (p.T + t.tc - 1) / t.tc;
+  int lt = 1;
+  while (lt < 8) {
+    const int nl = (nl1 + 2 * lt - 1) / (2 * lt);
+    if ((int64_t)nl * p.nKb * ntc < 2048) break;
+    lt *= 2;
+  }
+  return lt;
+}
+
+void apply_ctg_tile(Problem* p, const CtgTile& t) {
+  p->tile = t;
+  const int span = t.bl * t.wl * t.lt;
+  p->nLb = (p->Lp + span - 1) / span;
+}
+
 int ctg_tc_cap(int wl) {
   // LDS of the map-reduce block: tc * 64 doubles of outaged-branch flows and
   // tc * wl * 64 each of z and S
@@ -309,13 +331,13 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   }
   p->nKc = p->Kp / kCtgLanes;
   p->nLc = (p->Lp + kBlock - 1) / kBlock;
-  p->tile = CtgTile{8, 8, 0};
-  p->tile.tc = default_ctg_tc(*p, p->tile.wl);
+  CtgTile tile{8, 8, 0, 1};
+  tile.tc = default_ctg_tc(*p, tile.wl);
   p->nLb_max = p->Lp / 16;
   p->nKb_max = p->Kp / kCtgLanes;
-  p->nLb = p->Lp / (p->tile.bl * p->tile.wl);
-  if (p->Lp % (p->tile.bl * p->tile.wl)) p->nLb++;
   p->nKb = p->Kp / kCtgLanes;
+  tile.lt = default_ctg_lt(*p, tile);
+  apply_ctg_tile(p, tile);
   TermOffsets& to = p->toff;
   int o2 = 0;
   to.br = o2; o2 += p->nb_br;

@@ -118,6 +118,7 @@ struct CtgTile {
   int bl;   // branches per wavefront (8, 16 or 32)
   int wl;   // wavefronts per block, stacked along branches
   int tc;   // periods per block (the period range is split over grid.z)
+  int lt;   // consecutive tiles of wl * bl branches per block
 };
 
 // Homotopy source of one evaluation.
@@ -224,6 +225,8 @@ struct LoadBlock {
 void load_block(const Problem* p, const double* load_p, LoadBlock* out);
 DevWork carve_workspace(const Problem* p, void* ws);
 int default_ctg_tc(const Problem& p, int wl);
+int default_ctg_lt(const Problem& p, const CtgTile& t);  // tiles per block for tile t
+void apply_ctg_tile(Problem* p, const CtgTile& t);        // set the tile and the l-block count
 int ctg_tc_cap(int wl);  // most periods per block the LDS budget allows
 
 // Kernel launchers (qg_kernels.hip).  A step is kStages kernels.

@@ -50,7 +50,7 @@ struct EvalArgs {
   EvalMode mode;
   int fuse_adam;
   int nb_br, nb_bus, bus_chunks, nb_gen, nsplit;
-  int nLb, nKb, nKc, nLc, tc;
+  int nLb, nKb, nKc, nLc, tc, lt;
   TermOffsets toff;
   // contingencies scored this step (Alg. 2): slot s of the map-reduce holds
   // contingency act_k[s] (the identity when act_k is null), na slots in use,
@@ -802,8 +802,6 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
   const int TC = a.tc;
   const int t0 = blockIdx.z * TC;
   const int nt = min(TC, T - t0);
-  const int lbase = __builtin_amdgcn_readfirstlane(lb * BL * WL + wv * BL);
-  const bool on = lbase < Lp;
   const int k = kb * 64 + lane;  // slot of the lane
   double* sFk = dyn;
   double* zsh = dyn + TC * 64;
@@ -818,75 +816,87 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
   const double beta = w.params[PB_BETA];
   const R eps = (R)w.params[PB_EPS];
   const R eps2 = eps * eps;
-  R lod[BL], smx2[BL];
-  // lane e of chunk c holds F and qmax2 of period t0 + e / 8, branch
-  // lbase + 8 c + e % 8 (TC * 8 <= 64 entries)
-  R fv[BL / 8], qv[BL / 8];
-  if (on) {
-#pragma unroll
-    for (int j = 0; j < BL; ++j) {
-      lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
-      smx2[j] = (R)Sc[lbase + j];
-    }
-    const int et = lane >> 3, eg = lane & 7;
-#pragma unroll
-    for (int c = 0; c < BL / 8; ++c) {
-      fv[c] = R(0);
-      qv[c] = R(0);
-      if (et < nt) {
-        const size_t e = (size_t)(t0 + et) * Lp + lbase + c * 8 + eg;
-        fv[c] = (R)w.F[e];
-        qv[c] = (R)w.q2[e];
-      }
-    }
-  }
-  __syncthreads();
-  for (int tt = 0; tt < nt; ++tt) {
-    const int t = t0 + tt;
-    R zacc = R(0), sacc = R(0);
+  // the block covers a.lt consecutive tiles of WL * BL branches; z and S of
+  // each (period, wavefront, lane) accumulate over them in LDS
+  for (int it = 0; it < a.lt; ++it) {
+    const int lbase = __builtin_amdgcn_readfirstlane((lb * a.lt + it) * BL * WL + wv * BL);
+    const bool on = lbase < Lp;
+    R lod[BL], smx2[BL];
+    // lane e of chunk c holds F and qmax2 of period t0 + e / 8, branch
+    // lbase + 8 c + e % 8 (TC * 8 <= 64 entries)
+    R fv[BL / 8], qv[BL / 8];
     if (on) {
-      const R fk = (R)sFk[tt * 64 + lane];
-      const size_t o = ((size_t)kb * T + t) * Lp + lbase;
+#pragma unroll
+      for (int j = 0; j < BL; ++j) {
+        lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
+        smx2[j] = (R)Sc[lbase + j];
+      }
+      const int et = lane >> 3, eg = lane & 7;
 #pragma unroll
       for (int c = 0; c < BL / 8; ++c) {
-        R Fr[8], Qr[8], P[8], s2[8];
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          Fr[g] = readlane_any(fv[c], tt * 8 + g);
-          Qr[g] = readlane_any(qv[c], tt * 8 + g);
-        }
-        unsigned rows = 0;
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          const int j = c * 8 + g;
-          P[g] = fma_uniform_c(lod[j], fk, Fr[g]);
-          s2[g] = fma_uniform_c(P[g], P[g], Qr[g]);
-          if (__builtin_amdgcn_ballot_w64(s2[g] > smx2[j])) rows |= 1u << g;
-        }
-        if (rows) {
-          const R kt = (R)(Dc[t] * p.c_s * beta);
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            if ((rows >> g) & 1u) {
-              const int j = c * 8 + g;
-              R dP = R(0), dq = R(0);
-              if (s2[g] > smx2[j]) {
-                zacc += ctg_overload(P[g], s2[g], (R)Mc[lbase + j], eps, eps2, kt, dP, dq);
-                sacc = fma(lod[j], dP, sacc);
-              }
-              const R r = pair_sum(dP, dq);
-              if ((lane & 31) == 0) (lane ? w.qpart : w.rpart)[o + j] = (double)r;
-            }
-          }
-        }
-        if (lane < 8 && !((rows >> lane) & 1u)) {
-          w.rpart[o + c * 8 + lane] = 0.0;
-          w.qpart[o + c * 8 + lane] = 0.0;
+        fv[c] = R(0);
+        qv[c] = R(0);
+        if (et < nt) {
+          const size_t e = (size_t)(t0 + et) * Lp + lbase + c * 8 + eg;
+          fv[c] = (R)w.F[e];
+          qv[c] = (R)w.q2[e];
         }
       }
     }
-    zsh[(tt * WL + wv) * 64 + lane] = (double)zacc;
-    ssh[(tt * WL + wv) * 64 + lane] = (double)sacc;
+    if (it == 0) __syncthreads();  // sFk staged
+    for (int tt = 0; tt < nt; ++tt) {
+      const int t = t0 + tt;
+      R zacc = R(0), sacc = R(0);
+      if (on) {
+        const R fk = (R)sFk[tt * 64 + lane];
+        const size_t o = ((size_t)kb * T + t) * Lp + lbase;
+#pragma unroll
+        for (int c = 0; c < BL / 8; ++c) {
+          R Fr[8], Qr[8], P[8], s2[8];
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            Fr[g] = readlane_any(fv[c], tt * 8 + g);
+            Qr[g] = readlane_any(qv[c], tt * 8 + g);
+          }
+          unsigned rows = 0;
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            const int j = c * 8 + g;
+            P[g] = fma_uniform_c(lod[j], fk, Fr[g]);
+            s2[g] = fma_uniform_c(P[g], P[g], Qr[g]);
+            if (__builtin_amdgcn_ballot_w64(s2[g] > smx2[j])) rows |= 1u << g;
+          }
+          if (rows) {
+            const R kt = (R)(Dc[t] * p.c_s * beta);
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              if ((rows >> g) & 1u) {
+                const int j = c * 8 + g;
+                R dP = R(0), dq = R(0);
+                if (s2[g] > smx2[j]) {
+                  zacc += ctg_overload(P[g], s2[g], (R)Mc[lbase + j], eps, eps2, kt, dP, dq);
+                  sacc = fma(lod[j], dP, sacc);
+                }
+                const R r = pair_sum(dP, dq);
+                if ((lane & 31) == 0) (lane ? w.qpart : w.rpart)[o + j] = (double)r;
+              }
+            }
+          }
+          if (lane < 8 && !((rows >> lane) & 1u)) {
+            w.rpart[o + c * 8 + lane] = 0.0;
+            w.qpart[o + c * 8 + lane] = 0.0;
+          }
+        }
+      }
+      const int zi = (tt * WL + wv) * 64 + lane;
+      if (it == 0) {
+        zsh[zi] = (double)zacc;
+        ssh[zi] = (double)sacc;
+      } else {
+        zsh[zi] += (double)zacc;
+        ssh[zi] += (double)sacc;
+      }
+    }
   }
   // sum z and S over the block's wavefronts (wavefront order), every
   // (period, contingency) of the block by one thread
@@ -1377,6 +1387,7 @@ static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, 
   a.nKc = pr->nKc;
   a.nLc = pr->nLc;
   a.tc = pr->tile.tc;
+  a.lt = pr->tile.lt;
   a.toff = pr->toff;
   const Screen& sc = pr->scr;
   if (mode.screened) {

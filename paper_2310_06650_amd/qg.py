@@ -139,6 +139,7 @@ _sig = {
     "qg_time_stage": (C.c_int, [_vp, _vp, C.POINTER(qg_homotopy), C.c_int32, C.c_int32, _vp,
                                 _vp, C.POINTER(C.c_double)]),
     "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "qg_set_ctg_ltiles": (C.c_int, [_vp, C.c_int32]),
     "qg_eval_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp, _vp]),
     "qg_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double * QG_NCLASS,
                                C.POINTER(qg_adam_cfg), _vp]),
@@ -266,10 +267,10 @@ def qg_ctg_list(h, k):
 
 
 def qg_problem_dims(h):
-    out = np.zeros(17, dtype=np.int32)
-    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 17), "qg_problem_dims")
+    out = np.zeros(18, dtype=np.int32)
+    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 18), "qg_problem_dims")
     keys = ("N", "L", "G", "T", "M", "K", "Lp", "Kp", "G16", "G4", "Tp", "nLb", "nKb",
-            "ctg_bl", "ctg_wl", "ctg_tc", "lodf_kind")
+            "ctg_bl", "ctg_wl", "ctg_tc", "lodf_kind", "ctg_lt")
     return dict(zip(keys, (int(v) for v in out)))
 
 
@@ -367,8 +368,10 @@ class Problem:
     def ctg_list(self):
         return qg_ctg_list(self.handle, self.K)
 
-    def set_ctg_tile(self, bl, wl, tc=0):
+    def set_ctg_tile(self, bl, wl, tc=0, lt=None):
         qg_set_ctg_tile(self.handle, bl, wl, tc)
+        if lt is not None:
+            _check(lib.qg_set_ctg_ltiles(self.handle, int(lt)), "qg_set_ctg_ltiles")
         self.dims = qg_problem_dims(self.handle)
 
     def new_vector(self, host=None):

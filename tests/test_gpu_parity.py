@@ -153,17 +153,36 @@ def test_bitwise_deterministic(qg):
     assert np.array_equal(t1, t2) and np.array_equal(g1, g2)
 
 
-@pytest.mark.parametrize("bl,wl,tc", [(8, 2, 0), (8, 4, 1), (8, 4, 7), (16, 1, 0),
-                                      (16, 4, 5), (32, 2, 0), (32, 8, 3), (8, 8, 7)])
-def test_ctg_tile_invariance(qg, bl, wl, tc):
+@pytest.mark.parametrize("bl,wl,tc,lt", [(8, 2, 0, None), (8, 4, 1, None), (8, 4, 7, None),
+                                         (16, 1, 0, None), (16, 4, 5, None), (32, 2, 0, None),
+                                         (32, 8, 3, None), (8, 8, 7, None), (8, 8, 4, 2),
+                                         (8, 8, 4, 3), (8, 4, 2, 5), (16, 2, 3, 14)])
+def test_ctg_tile_invariance(qg, bl, wl, tc, lt):
+    """Tiles, including several branch tiles per block (the last block of a
+    ragged count holds fewer, or only padding)."""
     c = case("c2")
     prob = qg.Problem(c)
     x = synth.random_point(c, 10, spread=0.3)
     t0, g0 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
-    prob.set_ctg_tile(bl, wl, tc)
+    prob.set_ctg_tile(bl, wl, tc, lt=lt)
+    if lt is not None:
+        assert prob.dims["ctg_lt"] == lt
     t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
     np.testing.assert_allclose(t1, t0, rtol=1e-12)
     assert_grad_close(c, g1, g0, tol=1e-12)
+
+
+def test_ctg_branch_tiles_c3_against_oracle(qg):
+    """The 2,000-bus grid with two and eight branch tiles per block."""
+    c = case("c3")
+    x = synth.random_point(c, 7, spread=0.3)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
+    for lt in (2, 8):
+        prob = qg.Problem(c)
+        prob.set_ctg_tile(8, 8, 0, lt=lt)
+        t, g = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+        assert_terms_close(qg, t, tr)
+        assert_grad_close(c, g, gr)
 
 
 def test_ctg_tile_beyond_lds_budget_rejected(qg):
