@@ -45,7 +45,7 @@ def parse():
                     help="back-to-back launches per kernel for the per-kernel times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--ctg-tile", default="")
+    ap.add_argument("--ctg-tile", default="", help="bl x wl x tc [x lt] of the contingency map-reduce")
     ap.add_argument("--ctg-precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="storage and arithmetic of the contingency map-reduce")
     ap.add_argument("--eager", action="store_true",
@@ -188,7 +188,7 @@ def main():
     prob = qg.Problem(case, device="cuda:0", flags=flags[args.ctg_precision])
     if args.ctg_tile:
         parts = [int(v) for v in args.ctg_tile.split("x")]
-        prob.set_ctg_tile(*parts)
+        prob.set_ctg_tile(*parts[:3], lt=(parts[3] if len(parts) > 3 else None))
     stream = torch.cuda.Stream()
     prob.stream = stream
     x0 = synth.flat_start(case)
@@ -248,7 +248,8 @@ def main():
                                     f"{case.n_ctg}-contingency synthetic grid ({args.config})",
                            n_bus=case.n_bus, n_branch=case.n_branch, n_gen=case.n_gen,
                            n_period=case.n_period, n_ctg=case.n_ctg,
-                           ctg_tile=f"{prob.dims['ctg_bl']}x{prob.dims['ctg_wl']}x{prob.dims['ctg_tc']}",
+                           ctg_tile="x".join(str(prob.dims[k])
+                                             for k in ("ctg_bl", "ctg_wl", "ctg_tc", "ctg_lt")),
                            parallelism="single GPU"),
                kernel_us={k: round(v * 1e3, 3) for k, v in kms.items()},
                final_score=rep.final_score, roofline=roof)

@@ -1,8 +1,9 @@
 """Tile autotuner of the contingency map-reduce.
 
-The tile (branches per wavefront, wavefronts per block, periods per block)
-trades the re-reads of the outage factors against the number of blocks in
-flight; the best choice depends on the grid's shape.  ``tune`` times the
+The tile (branches per wavefront, wavefronts per block, periods per block,
+branch tiles per block) trades the re-reads of the outage factors and the
+per-block fixed costs against the number of blocks in flight; the best
+choice depends on the grid's shape.  ``tune`` times the
 three kernels the tile affects (map-reduce, per-contingency and per-branch
 reductions) for each candidate with qg_time_stage at a given point and keeps
 the fastest; results are cached per shape class (padded branch and
@@ -16,8 +17,10 @@ import os
 
 from . import qg
 
-CANDIDATES = [(8, 8, 2), (8, 4, 2), (8, 8, 4), (8, 4, 4), (8, 8, 7), (8, 4, 8), (16, 4, 2),
-              (16, 4, 4), (8, 2, 4), (16, 2, 8)]
+# (bl, wl, tc, lt); lt 0: the library's default for the other three
+CANDIDATES = [(8, 8, 2, 0), (8, 4, 2, 0), (8, 8, 4, 0), (8, 4, 4, 0), (8, 8, 7, 0), (8, 4, 8, 0),
+              (16, 4, 2, 0), (16, 4, 4, 0), (8, 2, 4, 0), (16, 2, 8, 0), (8, 8, 4, 1),
+              (8, 8, 7, 4), (8, 4, 8, 4), (8, 4, 8, 8)]
 
 
 def cache_path():
@@ -55,21 +58,22 @@ def tune(prob, x, reps=30, eps=1e-2, candidates=None, use_cache=True):
     (tile, {tile: microseconds})."""
     key = shape_key(prob)
     cache = _load() if use_cache else {}
-    if use_cache and key in cache:
+    if use_cache and key in cache and len(cache[key]["tile"]) == 4:
         tile = tuple(cache[key]["tile"])
-        prob.set_ctg_tile(*tile)
+        prob.set_ctg_tile(*tile[:3], lt=tile[3])
         return tile, cache[key]["times"]
     times = {}
-    for bl, wl, tc in (candidates or CANDIDATES):
+    for bl, wl, tc, lt in (candidates or CANDIDATES):
         try:
-            prob.set_ctg_tile(bl, wl, tc)
+            prob.set_ctg_tile(bl, wl, tc, lt=lt)
         except qg.QgError:
             continue
         us = sum(prob.time_stage(x, s, reps, eps) for s in (1, 2, 3))
-        times[f"{bl}x{wl}x{prob.dims['ctg_tc']}"] = us
+        d = prob.dims
+        times[f"{bl}x{wl}x{d['ctg_tc']}x{d['ctg_lt']}"] = us
     best = min(times, key=times.get)
     tile = tuple(int(v) for v in best.split("x"))
-    prob.set_ctg_tile(*tile)
+    prob.set_ctg_tile(*tile[:3], lt=tile[3])
     if use_cache:
         cache[key] = dict(tile=list(tile), times=times)
         _save(cache)

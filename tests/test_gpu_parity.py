@@ -435,10 +435,11 @@ def test_autotuner_picks_a_timed_tile_and_caches_it(qg, tmp_path, monkeypatch):
     prob = qg.Problem(c)
     x = prob.new_vector(synth.flat_start(c))
     tile, times = autotune.tune(prob, x, reps=5)
-    assert times and f"{tile[0]}x{tile[1]}x{tile[2]}" in times
-    assert times[f"{tile[0]}x{tile[1]}x{tile[2]}"] == min(times.values())
+    key = "x".join(str(v) for v in tile)
+    assert times and key in times
+    assert times[key] == min(times.values())
     d = prob.dims
-    assert (d["ctg_bl"], d["ctg_wl"], d["ctg_tc"]) == tile
+    assert (d["ctg_bl"], d["ctg_wl"], d["ctg_tc"], d["ctg_lt"]) == tile
     prob2 = qg.Problem(c)
     tile2, times2 = autotune.tune(prob2, prob2.new_vector(synth.flat_start(c)), reps=5)
     assert tile2 == tile and times2 == times   # from the cache
