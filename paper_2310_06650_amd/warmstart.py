@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import json
+import sys
 import time
 
 import numpy as np
@@ -222,12 +223,15 @@ def main():
     t0 = time.perf_counter()
     X, Y = generate(case, list(range(10000, 10000 + args.train)), args.solve_steps)
     t1 = time.perf_counter()
+    print(f"training data: {args.train} days in {t1 - t0:.1f} s", file=sys.stderr, flush=True)
     ws = WarmStart(case, X, Y, width=args.width, depth=args.depth)
     losses = ws.train(args.train_steps)
     t2 = time.perf_counter()
+    print(f"trained in {t2 - t1:.1f} s", file=sys.stderr, flush=True)
     runs = {}
     for n_warm in [int(v) for v in args.warm_steps.split(",")]:
         runs[n_warm] = compare(case, ws, list(range(20000, 20000 + args.test)), n_warm=n_warm)
+        print(f"compared with {n_warm}-step warm schedules", file=sys.stderr, flush=True)
     t3 = time.perf_counter()
     def med(rows, key):
         v = [r[key] for r in rows if r[key.split("_")[0] + "_steps"] > 0]
