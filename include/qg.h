@@ -86,6 +86,13 @@ enum { QG_CTG_ALL_NONBRIDGE = 0, QG_CTG_LIST = 1 };
  * the two may be set (ARG otherwise). */
 #define QG_FLAG_CTG_FP32 0x2u
 #define QG_FLAG_CTG_BF16 0x4u
+/* Aggregation over contingencies.  Default: per period the worst penalty
+ * plus the mean, max_k z_tk + (1/K) sum_k z_tk (the two contingency rows of
+ * Table 1).  With this flag: per period the plain sum sum_k z_tk (every
+ * scored contingency's gradient handed to Adam with weight 1, as Alg. 2
+ * accumulates them); the sum goes into the QG_T_CTG_MEAN slot and
+ * QG_T_CTG_MAX is 0. */
+#define QG_FLAG_CTG_SUM 0x8u
 
 /* Grid description: host arrays, all FP64 per unit (100 MVA base) unless
  * stated; prices in $ per pu-hour, durations in hours. */

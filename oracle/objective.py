@@ -45,7 +45,9 @@ Readings of the paper fixed here (the text is silent or ambiguous):
 * Branch pi-model with tap 1, no phase shift: flows of the GO3 branch model,
   consistent with the partial derivative printed in Section II-G.
 * The per-period aggregation over contingencies (max plus mean) follows the
-  two contingency rows of Table 1; the outaged branch itself is excluded.
+  two contingency rows of Table 1; the plain sum over k (Alg. 2 adds every
+  backpropagated contingency gradient) is the alternative; the outaged
+  branch itself is excluded.
 * The DC injection of a bus is generation minus load; a uniform slack
   removes the period mean before the flow solve (so eq. (correction) is the
   exact gradient).
@@ -222,8 +224,14 @@ def qmax2(fl):
 # full evaluation
 # --------------------------------------------------------------------------
 
-def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None, active=None):
+def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None, active=None,
+             agg="max_mean"):
     """Objective terms (dict) and, if asked, the gradient (flat, like x).
+
+    agg: "max_mean" (per period the worst penalty plus the mean over the K
+    contingencies, Table 1's two rows) or "sum" (per period the plain sum,
+    the accumulation of Alg. 2; reported in the "ctg_mean" slot, "ctg_max"
+    is 0).
 
     active: None (every contingency is scored) or the positions (into
     model.ctg) of the contingencies scored this step, as in the contingency
@@ -336,8 +344,12 @@ def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None, activ
         z[t] = kct[t] * sig.sum(axis=0)
     z[:, ~act] = (kct * (L - 1) * eps)[:, None]
     kstar = np.argmax(z, axis=1) if K > 0 else np.zeros(T, dtype=np.int64)
-    terms["ctg_max"] = float(z[np.arange(T), kstar].sum()) if K > 0 else 0.0
-    terms["ctg_mean"] = float(z.mean(axis=1).sum()) if K > 0 else 0.0
+    if agg == "sum":
+        terms["ctg_max"] = 0.0
+        terms["ctg_mean"] = float(z.sum())
+    else:
+        terms["ctg_max"] = float(z[np.arange(T), kstar].sum()) if K > 0 else 0.0
+        terms["ctg_mean"] = float(z.mean(axis=1).sum()) if K > 0 else 0.0
 
     terms["load_value"] = float((dt[:, None] * case.load_value * case.load_p).sum())
     terms["total"] = (terms["dev"] + terms["bal"] + terms["br"] + terms["ang"]
@@ -352,9 +364,12 @@ def evaluate(model, x, eps, beta, rho_scale, want_grad=True, t_chunk=None, activ
     Qc = np.zeros((T, L))       # dC/d qmax2
     if K > 0:
         for t in chunks:
-            w = np.where(act, 1.0 / K, 0.0)
-            if act[kstar[t]]:
-                w[kstar[t]] += 1.0
+            if agg == "sum":
+                w = np.where(act, 1.0, 0.0)
+            else:
+                w = np.where(act, 1.0 / K, 0.0)
+                if act[kstar[t]]:
+                    w[kstar[t]] += 1.0
             Pk = F[t][:, None] + model.lodf * F[t, model.ctg][None, :]
             s = np.sqrt(Pk * Pk + q2[t][:, None])
             ds = soft_relu_grad(s - sctg[:, None], eps)

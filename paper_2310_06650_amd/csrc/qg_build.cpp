@@ -313,7 +313,8 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   p->n_x = 2LL * T * N + 4LL * T * G;
   if ((o->flags & QG_FLAG_CTG_FP32) && (o->flags & QG_FLAG_CTG_BF16))
     return fail(QG_ERR_ARG, "at most one contingency precision flag");
-  if (o->flags & ~(uint32_t)(QG_FLAG_CHECK_FINITE | QG_FLAG_CTG_FP32 | QG_FLAG_CTG_BF16))
+  if (o->flags & ~(uint32_t)(QG_FLAG_CHECK_FINITE | QG_FLAG_CTG_FP32 | QG_FLAG_CTG_BF16 |
+                             QG_FLAG_CTG_SUM))
     return fail(QG_ERR_ARG, "unknown build flag");
   p->flags = o->flags;
   p->nb_br = (int)((int64_t(T) * L + kBlock - 1) / kBlock);
@@ -693,6 +694,7 @@ void rebase_pointers(Problem* p, void* arena) {
   dp.load_p = D(36); dp.load_q = D(37); dp.dt = D(38); dp.rsv_req = D(39);
   dp.sum_load = D(40); dp.isf_gT = D(41); dp.isf_ga = D(42);
   dp.lodf_kind = lodf_kind_of(p->flags);
+  dp.ctg_sum = (p->flags & QG_FLAG_CTG_SUM) ? 1 : 0;
   dp.lodf = dp.lodf_kind == kLodfF64 ? D(43) : nullptr;
   dp.lodf32 = dp.lodf_kind == kLodfF32 ? reinterpret_cast<const float*>(base + cl.off[43]) : nullptr;
   dp.lodf16 =

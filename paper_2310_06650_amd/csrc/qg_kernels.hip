@@ -938,7 +938,7 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
     const int k = a.act_k ? a.act_k[s] : s;
     z = kt * ((double)(L - 1) * eps + zs);
     w.zval[(size_t)t * Kp + k] = z;
-    w.smean[o] = ss / (double)K;
+    w.smean[o] = p.ctg_sum ? ss : ss / (double)K;
     idx = k;
     zsum = z;
   }
@@ -1026,15 +1026,18 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
       zsum += ssum;
     }
     if (!(kstar >= 0 && kstar < K)) kstar = 0;  // NaN penalties: keep every index in range
+    // weight of every scored contingency: 1/K for the mean (plus 1 for the
+    // period's worst), or 1 for the plain sum
     const double invK = 1.0 / (double)K;
+    const double wk = p.ctg_sum ? 1.0 : invK;
     if (hasl) {
-      r *= invK;
-      q *= invK;
+      r *= wk;
+      q *= wk;
       // the outaged branch's own factor is NaN: it never tests overloaded
       const double lo = lodf_value(p, l, kstar);
       const double P = fma(lo, w.Fk[(size_t)t * Kp + kstar], Fl);
       const double s2 = fma(P, P, q2l);
-      if (s2 > sm2) {
+      if (!p.ctg_sum && s2 > sm2) {
         double dP, dq;
         ctg_overload(P, s2, sm, eps, eps * eps, kt, dP, dq);
         r += dP;
@@ -1047,10 +1050,10 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
       }
     }
     if (lc == 0 && tid == 0) {
-      w.tpart[a.toff.cmax + t] = zmax;
+      w.tpart[a.toff.cmax + t] = p.ctg_sum ? 0.0 : zmax;
       // contingencies not scored this step take their no-overload penalty
       const double rest = (double)(K - a.na) * (kt * ((double)(L - 1) * eps));
-      w.tpart[a.toff.cmean + t] = (zsum + rest) * invK;
+      w.tpart[a.toff.cmean + t] = (zsum + rest) * wk;
       w.kstar[t] = (double)kstar;
     }
   } else if (lc == 0 && tid == 0) {

@@ -41,6 +41,7 @@ QG_CTG_ALL_NONBRIDGE, QG_CTG_LIST = 0, 1
 QG_FLAG_CHECK_FINITE = 0x1
 QG_FLAG_CTG_FP32 = 0x2
 QG_FLAG_CTG_BF16 = 0x4
+QG_FLAG_CTG_SUM = 0x8
 KERNEL_NAMES = ("k_forward", "k_ctg_main", "k_ctg_zred", "k_ctg_asm", "k_adjoint", "k_final")
 
 _pd = C.POINTER(C.c_double)

@@ -443,3 +443,24 @@ def test_autotuner_picks_a_timed_tile_and_caches_it(qg, tmp_path, monkeypatch):
     prob2 = qg.Problem(c)
     tile2, times2 = autotune.tune(prob2, prob2.new_vector(synth.flat_start(c)), reps=5)
     assert tile2 == tile and times2 == times   # from the cache
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_sum_aggregation(qg, name):
+    """QG_FLAG_CTG_SUM: per-period sum over contingencies (also with a
+    screened set)."""
+    c = case(name)
+    x = synth.random_point(c, 17, spread=0.3)
+    prob = qg.Problem(c, flags=qg.QG_FLAG_CTG_SUM)
+    t, g = gpu_eval(qg, prob, x, 1e-2, 0.9, 1.0)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 0.9, 1.0, agg="sum")
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+    K = prob.K
+    A = np.sort(np.random.default_rng(3).choice(K, size=max(1, K // 3), replace=False))
+    prob.set_screening(top_frac=len(A) / K)
+    prob.set_active_contingencies(A)
+    t, g = gpu_eval(qg, prob, x, 1e-2, 0.9, 1.0)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 0.9, 1.0, agg="sum", active=A)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)

@@ -380,3 +380,42 @@ def test_thermal_and_angle_exact_two_bus():
     s = 2.0 * math.sin(d / 2) / 0.1
     assert abs(t["br"] - c.c_s * (s - 1.0)) < 1e-9 * c.c_s
     assert abs(t["ang"] - c.c_ang * (d - 0.3)) < 1e-9 * c.c_ang
+
+
+# ---------------------------------------------------------------- sum aggregation
+
+def test_sum_aggregation_is_k_times_the_mean_and_matches_bruteforce():
+    c = synth.config_case("c1")
+    m = ob.make_model(c)
+    x = synth.random_point(c, 3)
+    K = len(m.ctg)
+    ts, _ = ob.evaluate(m, x, 0.02, 0.9, 1.0, want_grad=False, agg="sum")
+    tm, _ = ob.evaluate(m, x, 0.02, 0.9, 1.0, want_grad=False)
+    assert ts["ctg_max"] == 0.0
+    assert abs(ts["ctg_mean"] - K * tm["ctg_mean"]) <= 1e-12 * ts["ctg_mean"]
+    _, _, zb = ob.ctg_term_bruteforce(m, x, 0.02, 0.9, return_z=True)
+    assert abs(ts["ctg_mean"] - zb.sum()) <= 1e-10 * ts["ctg_mean"]
+    for k in ob.TERMS:
+        if k not in ("ctg_max", "ctg_mean"):
+            assert ts[k] == tm[k]
+
+
+def test_sum_aggregation_gradient_matches_central_differences():
+    c = synth.config_case("c1")
+    m = ob.make_model(c)
+    x = synth.random_point(c, 5)
+    eps, beta, rho = 0.05, 0.7, 0.8
+    _, g = ob.evaluate(m, x, eps, beta, rho, agg="sum")
+    rng = np.random.default_rng(4)
+    for s in c.block_slices()[:4]:
+        idx = rng.choice(np.arange(s.start, s.stop), size=12, replace=False)
+        fd = []
+        for j in idx:
+            h = 1e-6 * max(1.0, abs(x[j]))
+            xp = x.copy(); xp[j] += h
+            xm = x.copy(); xm[j] -= h
+            fp = ob.evaluate(m, xp, eps, beta, rho, want_grad=False, agg="sum")[0]
+            fm = ob.evaluate(m, xm, eps, beta, rho, want_grad=False, agg="sum")[0]
+            fd.append(sum(fp[k] - fm[k] for k in ob.TERMS if k != "load_value") / (2 * h))
+        err = np.abs(np.array(fd) - g[idx]).max() / max(np.abs(g[s]).max(), 1e-30)
+        assert err < 2e-7, (s, err)
