@@ -141,3 +141,20 @@ def test_load_draws_keep_the_grid():
     assert np.allclose(rr, 0.1 * lp.sum(axis=1))
     c2 = synth.with_loads(c, a)
     assert c2.n_bus == c.n_bus and np.array_equal(c2.br_x, c.br_x)
+
+
+def test_sum_flag_and_period_limit():
+    c = synth.config_case("c1")
+    base = _sizes(c)
+    s = _sizes(c, flags=qg.QG_FLAG_CTG_SUM | qg.QG_FLAG_CTG_FP32)
+    assert s.n_x == base.n_x and s.workspace_bytes == base.workspace_bytes
+    c65 = synth.config_case("c1")
+    c65.n_period = 65
+    T = 65
+    c65.load_p = np.tile(c.load_p[:1], (T, 1))
+    c65.load_q = np.tile(c.load_q[:1], (T, 1))
+    c65.reserve_req = np.full(T, c.reserve_req[0])
+    c65.dt = np.ones(T)
+    with pytest.raises(qg.QgError) as e:
+        _sizes(c65)
+    assert e.value.status == qg.QG_ERR_ARG
