@@ -388,7 +388,7 @@ qg_status qg_screen_bytes(const qg_problem* prob, const qg_screen_opts* opts, si
  * 256-byte aligned, used until screening is turned off or reconfigured (it
  * holds the set, the severities and the set's outage factors gathered into
  * contiguous columns).  No set is chosen yet: until one is, evaluations
- * score every contingency.  A step graph cached by qg_solve is dropped.
+ * score every contingency.  Does no device work (stream is unused).  A step graph cached by qg_solve is dropped.
  * With screening on and a set chosen, qg_eval_grad and qg_time_stage
  * evaluate the screened objective; qg_solve_batch and qg_solve with
  * profile = 1 refuse a problem with screening on.

@@ -210,7 +210,7 @@ qg_status qg_screen_bytes(const qg_problem* pr, const qg_screen_opts* o, size_t*
 
 qg_status qg_set_screening(qg_problem* pr, const qg_screen_opts* o, void* d_buf, size_t bytes,
                            void* stream) {
-  (void)stream;
+  (void)stream;  // no device work: the buffer is written by the first selection
   qg_status s = check_problem(pr);
   if (s != QG_OK) return s;
   qg::Problem& p = pr->p;
@@ -539,9 +539,16 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   // profile: events around every kernel of up to kProfSteps queued steps,
   // read after one synchronisation, so host latency does not enter the times
   constexpr int kKernels = qg::kStages, kProfSteps = 32, kEv = kKernels + 1;
-  std::vector<hipEvent_t> evs;
+  struct Events {  // destroyed on every return path
+    std::vector<hipEvent_t> v;
+    ~Events() {
+      for (auto& e : v)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } ev_hold;
+  std::vector<hipEvent_t>& evs = ev_hold.v;
   if (profile) {
-    evs.resize(kProfSteps * kEv);
+    evs.assign(kProfSteps * kEv, nullptr);
     for (auto& e : evs) HIP_TRY(hipEventCreate(&e), "event");
   }
 
@@ -713,7 +720,6 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   if (profile) {
     for (int q = 0; q < kKernels; ++q)
       if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
-    for (auto& e : evs) (void)hipEventDestroy(e);
   }
   return QG_OK;
 }
