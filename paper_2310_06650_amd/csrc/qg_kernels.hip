@@ -191,6 +191,11 @@ __device__ __forceinline__ float readlane_any(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 __device__ __forceinline__ double readlane_any(double v, int lane) { return readlane_f64(v, lane); }
+// v with lane `lane` replaced by the wavefront-uniform x
+template <typename R>
+__device__ __forceinline__ R writelane_any(R v, R x, int lane) {
+  return (int)(threadIdx.x & 63) == lane ? x : v;
+}
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
@@ -844,12 +849,20 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
       }
     }
     if (it == 0) __syncthreads();  // sFk staged
+    // R and Q of (period t0 + e / 8, branch lbase + 8 c + e % 8) gather in
+    // lane e of racc[c], qacc[c] (zero where nothing is overloaded) and go
+    // out once per tile, so the period loop itself stores nothing
+    R racc[BL / 8], qacc[BL / 8];
+#pragma unroll
+    for (int c = 0; c < BL / 8; ++c) {
+      racc[c] = R(0);
+      qacc[c] = R(0);
+    }
     for (int tt = 0; tt < nt; ++tt) {
       const int t = t0 + tt;
       R zacc = R(0), sacc = R(0);
       if (on) {
         const R fk = (R)sFk[tt * 64 + lane];
-        const size_t o = ((size_t)kb * T + t) * Lp + lbase;
 #pragma unroll
         for (int c = 0; c < BL / 8; ++c) {
           R Fr[8], Qr[8], P[8], s2[8];
@@ -877,14 +890,11 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
                   zacc += ctg_overload(P[g], s2[g], (R)Mc[lbase + j], eps, eps2, kt, dP, dq);
                   sacc = fma(lod[j], dP, sacc);
                 }
-                const R r = pair_sum(dP, dq);
-                if ((lane & 31) == 0) (lane ? w.qpart : w.rpart)[o + j] = (double)r;
+                const R r = pair_sum(dP, dq);  // lane 0: sum of dP, lane 32: of dq
+                racc[c] = writelane_any(racc[c], readlane_any(r, 0), tt * 8 + g);
+                qacc[c] = writelane_any(qacc[c], readlane_any(r, 32), tt * 8 + g);
               }
             }
-          }
-          if (lane < 8 && !((rows >> lane) & 1u)) {
-            w.rpart[o + c * 8 + lane] = 0.0;
-            w.qpart[o + c * 8 + lane] = 0.0;
           }
         }
       }
@@ -895,6 +905,14 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
       } else {
         zsh[zi] += (double)zacc;
         ssh[zi] += (double)sacc;
+      }
+    }
+    if (on && lane < nt * 8) {
+      const size_t o = ((size_t)kb * T + t0 + (lane >> 3)) * Lp + lbase + (lane & 7);
+#pragma unroll
+      for (int c = 0; c < BL / 8; ++c) {
+        w.rpart[o + c * 8] = (double)racc[c];
+        w.qpart[o + c * 8] = (double)qacc[c];
       }
     }
   }
