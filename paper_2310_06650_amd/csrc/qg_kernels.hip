@@ -865,7 +865,7 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
         const R fk = (R)sFk[tt * 64 + lane];
 #pragma unroll
         for (int c = 0; c < BL / 8; ++c) {
-          R Fr[8], Qr[8], P[8], s2[8];
+          R Fr[8], Qr[8], P[8];
 #pragma unroll
           for (int g = 0; g < 8; ++g) {
             Fr[g] = readlane_any(fv[c], tt * 8 + g);
@@ -876,8 +876,8 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
           for (int g = 0; g < 8; ++g) {
             const int j = c * 8 + g;
             P[g] = fma_uniform_c(lod[j], fk, Fr[g]);
-            s2[g] = fma_uniform_c(P[g], P[g], Qr[g]);
-            if (__builtin_amdgcn_ballot_w64(s2[g] > smx2[j])) rows |= 1u << g;
+            const R s2 = fma_uniform_c(P[g], P[g], Qr[g]);
+            if (__builtin_amdgcn_ballot_w64(s2 > smx2[j])) rows |= 1u << g;
           }
           if (rows) {
             const R kt = (R)(Dc[t] * p.c_s * beta);
@@ -885,9 +885,13 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
             for (int g = 0; g < 8; ++g) {
               if ((rows >> g) & 1u) {
                 const int j = c * 8 + g;
+                // the square is formed again (the same fused operation, so
+                // the same value) rather than kept across the test of all
+                // eight branches: fewer live registers
+                const R s2 = fma(P[g], P[g], Qr[g]);
                 R dP = R(0), dq = R(0);
-                if (s2[g] > smx2[j]) {
-                  zacc += ctg_overload(P[g], s2[g], (R)Mc[lbase + j], eps, eps2, kt, dP, dq);
+                if (s2 > smx2[j]) {
+                  zacc += ctg_overload(P[g], s2, (R)Mc[lbase + j], eps, eps2, kt, dP, dq);
                   sacc = fma(lod[j], dP, sacc);
                 }
                 const R r = pair_sum(dP, dq);  // lane 0: sum of dP, lane 32: of dq
