@@ -327,9 +327,10 @@ def test_no_contingency_grid(qg):
     assert_grad_close(c, g, gr)
 
 
-@pytest.mark.parametrize("T", [1, 17, 33, 48])
+@pytest.mark.parametrize("T", [1, 17, 33, 48, 49, 64])
 def test_ragged_sizes(qg, T):
-    """Sizes that are not multiples of any tile: N=37, L=71, K ragged, T odd."""
+    """Sizes that are not multiples of any tile: N=37, L=71, K ragged, T odd;
+    up to the largest period count (64: four 16-row MFMA tiles)."""
     c = synth.make_case(seed=40 + T, n_bus=37, n_branch=71, n_gen=9, n_period=T, n_ctg=None)
     prob = qg.Problem(c)
     x = synth.random_point(c, T)
