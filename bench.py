@@ -45,7 +45,9 @@ def parse():
                     help="back-to-back launches per kernel for the per-kernel times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--ctg-tile", default="", help="bl x wl x tc [x lt] of the contingency map-reduce")
+    ap.add_argument("--ctg-tile", default="",
+                    help="tile of the contingency map-reduce: s<wl>x<tcw>[x<lt>] (period-split) "
+                         "or <bl>x<wl>x<tc>[x<lt>] (branch-stacked)")
     ap.add_argument("--ctg-precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="storage and arithmetic of the contingency map-reduce")
     ap.add_argument("--eager", action="store_true",
@@ -187,8 +189,7 @@ def main():
     flags = {"fp64": 0, "fp32": qg.QG_FLAG_CTG_FP32, "bf16": qg.QG_FLAG_CTG_BF16}
     prob = qg.Problem(case, device="cuda:0", flags=flags[args.ctg_precision])
     if args.ctg_tile:
-        parts = [int(v) for v in args.ctg_tile.split("x")]
-        prob.set_ctg_tile(*parts[:3], lt=(parts[3] if len(parts) > 3 else None))
+        prob.set_tile(args.ctg_tile)
     stream = torch.cuda.Stream()
     prob.stream = stream
     x0 = synth.flat_start(case)
@@ -248,8 +249,7 @@ def main():
                                     f"{case.n_ctg}-contingency synthetic grid ({args.config})",
                            n_bus=case.n_bus, n_branch=case.n_branch, n_gen=case.n_gen,
                            n_period=case.n_period, n_ctg=case.n_ctg,
-                           ctg_tile="x".join(str(prob.dims[k])
-                                             for k in ("ctg_bl", "ctg_wl", "ctg_tc", "ctg_lt")),
+                           ctg_tile=prob.tile(),
                            parallelism="single GPU"),
                kernel_us={k: round(v * 1e3, 3) for k, v in kms.items()},
                final_score=rep.final_score, roofline=roof)

@@ -293,31 +293,50 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
  * Tp = T up to 16; nLb, nKb = partial-sum counts of the contingency
  * map-reduce; ctg_bl, ctg_wl, ctg_tc = its tile).  With capacity >= 17,
  * dims[16] = storage of the outage factors (0 FP64, 1 FP32, 2 BF16); with
- * capacity >= 18, dims[17] = branch tiles per block (qg_set_ctg_ltiles).
+ * capacity >= 18, dims[17] = branch tiles per block (qg_set_ctg_ltiles);
+ * capacity >= 19, dims[18] = 1 for a period-split tile (qg_set_ctg_tile_split).
  * capacity must be >= 16.
  */
 qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacity);
 
 /*
- * Tile of the contingency map-reduce: bl branches per wavefront (8, 16 or 32),
- * wl wavefronts per block (1, 2, 4 or 8) with bl*wl >= 16, and tc periods per
- * block (0: a default from the problem size; at most 8, and at most T).  The
- * results do not depend on the tile except through the order of
- * floating-point sums.  A step graph cached by qg_solve is re-captured after
- * a change.  Errors: ARG.
+ * Branch-stacked tile of the contingency map-reduce: bl branches per
+ * wavefront (8, 16 or 32), wl wavefronts per block (1, 2, 4 or 8) stacked
+ * along the branches with bl*wl >= 16, and tc periods per block (0: a default
+ * from the problem size; at most 8, and at most T).  A new problem starts
+ * with the period-split tile of qg_set_ctg_tile_split (wl 4, tcw 2 below 32
+ * periods and 4 from there, default lt).  The results do not depend on the
+ * tile except through the order of floating-point sums.  A step graph cached
+ * by qg_solve is re-captured after a change.  Errors: ARG.
  */
 qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
 
 /*
- * Branch tiles (of wl * bl branches) that one block of the contingency
- * map-reduce covers, lt in [1, 64], or 0 for the default (doubling from 1
- * while at least 2048 blocks remain).  More tiles per block spread each
- * block's fixed costs and shrink the per-(period, contingency) partial sums;
- * fewer leave more blocks.  qg_set_ctg_tile resets it to the default.
+ * Branch tiles (of wl * bl branches; of 8 branches for a period-split tile)
+ * that one block of the contingency map-reduce covers, lt in [1, 64] (at
+ * least 2 for a period-split tile), or 0 for the default (doubling from 1,
+ * or 2, while at least 2048 blocks remain, at most 8).  More tiles per block
+ * spread each block's fixed costs and shrink the per-(period, contingency)
+ * partial sums; fewer leave more blocks.  qg_set_ctg_tile and
+ * qg_set_ctg_tile_split reset it to the default.
  * Results depend on it only through the order of floating-point sums.  A
  * step graph cached by qg_solve is re-captured after a change.  Errors: ARG.
  */
 qg_status qg_set_ctg_ltiles(qg_problem* prob, int32_t lt);
+
+/*
+ * Period-split tile of the contingency map-reduce (the default form): a
+ * block of wl wavefronts (1..8) covers lt consecutive tiles of 8 branches (lt
+ * in [2, 64], or 0 for the default of qg_set_ctg_ltiles) and 64
+ * contingencies, and its wavefronts split the periods, tcw (1..8) each, so a
+ * block spans wl * tcw periods.  A wavefront's per-(period, contingency) sums
+ * stay with it over the block's whole branch range (no sum over wavefronts);
+ * with wl * tcw >= T each outage factor is read once per evaluation.
+ * Results depend on the tile only through the order of floating-point sums.
+ * qg_set_ctg_tile returns to the branch-stacked form.  A step graph cached by
+ * qg_solve is re-captured after a change.  Errors: ARG.
+ */
+qg_status qg_set_ctg_tile_split(qg_problem* prob, int32_t wl, int32_t tcw, int32_t lt);
 
 /*
  * Test support: copy an intermediate array of the last evaluation from the

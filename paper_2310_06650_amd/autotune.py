@@ -1,9 +1,11 @@
 """Tile autotuner of the contingency map-reduce.
 
-The tile (branches per wavefront, wavefronts per block, periods per block,
-branch tiles per block) trades the re-reads of the outage factors and the
-per-block fixed costs against the number of blocks in flight; the best
-choice depends on the grid's shape.  ``tune`` times the
+The tile (period-split: wavefronts per block, periods per wavefront, branch
+tiles per block; branch-stacked: branches per wavefront, wavefronts per
+block, periods per block, branch tiles per block) trades the re-reads of the
+outage factors, the partial sums and the per-block fixed costs against the
+number of blocks in flight; the best choice depends on the grid's shape.
+Tiles are named by their text form (``Problem.tile``).  ``tune`` times the
 three kernels the tile affects (map-reduce, per-contingency and per-branch
 reductions) for each candidate with qg_time_stage at a given point and keeps
 the fastest; results are cached per shape class (padded branch and
@@ -17,10 +19,9 @@ import os
 
 from . import qg
 
-# (bl, wl, tc, lt); lt 0: the library's default for the other three
-CANDIDATES = [(8, 8, 2, 0), (8, 4, 2, 0), (8, 8, 4, 0), (8, 4, 4, 0), (8, 8, 7, 0), (8, 4, 8, 0),
-              (16, 4, 2, 0), (16, 4, 4, 0), (8, 2, 4, 0), (16, 2, 8, 0), (8, 8, 4, 1),
-              (8, 8, 7, 4), (8, 4, 8, 4), (8, 4, 8, 8)]
+# text forms; a missing lt: the library's default for the rest of the tile
+CANDIDATES = ["s4x2", "s4x4", "s2x2", "s8x2", "s4x3", "s4x6", "s8x6", "s4x4x16", "s4x2x4",
+              "8x8x4", "8x4x4", "8x8x7", "16x4x4", "8x8x4x1", "8x8x7x4", "8x4x8x8"]
 
 
 def cache_path():
@@ -58,23 +59,21 @@ def tune(prob, x, reps=30, eps=1e-2, candidates=None, use_cache=True):
     (tile, {tile: microseconds})."""
     key = shape_key(prob)
     cache = _load() if use_cache else {}
-    if use_cache and key in cache and len(cache[key]["tile"]) == 4:
-        tile = tuple(cache[key]["tile"])
-        prob.set_ctg_tile(*tile[:3], lt=tile[3])
+    if use_cache and key in cache and isinstance(cache[key].get("tile"), str):
+        tile = cache[key]["tile"]
+        prob.set_tile(tile)
         return tile, cache[key]["times"]
     times = {}
-    for bl, wl, tc, lt in (candidates or CANDIDATES):
+    for cand in (candidates or CANDIDATES):
         try:
-            prob.set_ctg_tile(bl, wl, tc, lt=lt)
+            prob.set_tile(cand)
         except qg.QgError:
             continue
         us = sum(prob.time_stage(x, s, reps, eps) for s in (1, 2, 3))
-        d = prob.dims
-        times[f"{bl}x{wl}x{d['ctg_tc']}x{d['ctg_lt']}"] = us
-    best = min(times, key=times.get)
-    tile = tuple(int(v) for v in best.split("x"))
-    prob.set_ctg_tile(*tile[:3], lt=tile[3])
+        times[prob.tile()] = us
+    tile = min(times, key=times.get)
+    prob.set_tile(tile)
     if use_cache:
-        cache[key] = dict(tile=list(tile), times=times)
+        cache[key] = dict(tile=tile, times=times)
         _save(cache)
     return tile, times

@@ -81,7 +81,7 @@ def main():
         buses=int(sum(c.n_bus for c in cases)), periods_mean=float(np.mean([c.n_period for c in cases])),
         contingency_elements_per_step=int(elems), lodf_bytes=int(lodf_bytes),
         build_s=build_s, tune_s=tune_s,
-        tiles={f"{c.n_bus}x{c.n_period}": (list(t) if t else None) for c, t in zip(cases, tiles)},
+        tiles={f"{c.n_bus}x{c.n_period}": t for c, t in zip(cases, tiles)},
         sequential=dict(seconds=seq_s, scenario_steps_per_s=args.n * args.steps / seq_s,
                         elements_per_s=elems * args.steps / seq_s),
         batched=dict(seconds=batch_s, scenario_steps_per_s=args.n * args.steps / batch_s,

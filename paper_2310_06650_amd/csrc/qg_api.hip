@@ -190,10 +190,10 @@ qg_status qg_problem_dims(const qg_problem* pr, int32_t* d, int32_t capacity) {
   if (s != QG_OK) return s;
   if (!d || capacity < 16) return fail(QG_ERR_ARG, "dims needs 16 entries");
   const qg::Problem& p = pr->p;
-  const int32_t v[18] = {p.N,  p.L,   p.G,   p.T,       p.M,       p.K,       p.Lp,
+  const int32_t v[19] = {p.N,  p.L,   p.G,   p.T,       p.M,       p.K,       p.Lp,
                          p.Kp, p.G16, p.G4,  p.Tp,      p.nLb,     p.nKb,     p.tile.bl,
-                         p.tile.wl,   p.tile.tc, p.dp.lodf_kind, p.tile.lt};
-  std::memcpy(d, v, sizeof(int32_t) * (capacity >= 18 ? 18 : capacity >= 17 ? 17 : 16));
+                         p.tile.wl,   p.tile.tc, p.dp.lodf_kind, p.tile.lt, p.tile.split};
+  std::memcpy(d, v, sizeof(int32_t) * (capacity < 19 ? capacity : 19));
   return QG_OK;
 }
 
@@ -339,12 +339,25 @@ qg_status qg_set_ctg_tile(qg_problem* pr, int32_t bl, int32_t wl, int32_t tc) {
   return QG_OK;
 }
 
+qg_status qg_set_ctg_tile_split(qg_problem* pr, int32_t wl, int32_t tcw, int32_t lt) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (wl < 1 || wl > 8 || tcw < 1 || tcw > qg::kCtgMaxTc || lt == 1 || lt < 0 || lt > 64)
+    return fail(QG_ERR_ARG, "split tile needs wl in [1, 8], tcw in [1, 8], lt 0 or in [2, 64]");
+  qg::CtgTile t{8, wl, tcw, lt};
+  t.split = 1;
+  if (lt == 0) t.lt = qg::default_ctg_lt(pr->p, t);
+  qg::apply_ctg_tile(&pr->p, t);
+  return QG_OK;
+}
+
 qg_status qg_set_ctg_ltiles(qg_problem* pr, int32_t lt) {
   qg_status s = check_problem(pr);
   if (s != QG_OK) return s;
   if (lt < 0 || lt > 64) return fail(QG_ERR_ARG, "lt must lie in [0, 64]");
   qg::Problem& p = pr->p;
   qg::CtgTile t = p.tile;
+  if (t.split && lt == 1) return fail(QG_ERR_ARG, "a period-split tile needs lt >= 2");
   t.lt = lt > 0 ? lt : qg::default_ctg_lt(p, t);
   qg::apply_ctg_tile(&p, t);
   return QG_OK;
@@ -579,7 +592,7 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     // and so is the contingency tile (grid and LDS size of the map-reduce)
     const qg::CtgTile& gt = pr->p.graph_tile;
     if (hit && (gt.bl != p.tile.bl || gt.wl != p.tile.wl || gt.tc != p.tile.tc ||
-                gt.lt != p.tile.lt))
+                gt.lt != p.tile.lt || gt.split != p.tile.split))
       hit = false;
     if (!hit) {
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; pr->p.graph_exec = nullptr; }
@@ -711,7 +724,10 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   rep->wall_s = std::chrono::duration<double>(clock::now() - t_start).count();
   // objective at the last schedule point was left in the workspace terms
   double last[QG_NTERMS];
-  HIP_TRY(hipMemcpy(last, w.terms, sizeof(last), hipMemcpyDeviceToHost), "terms read");
+  // on the solve's own stream: a legacy-stream copy would conflict with a
+  // graph capture running on another thread
+  HIP_TRY(hipMemcpyAsync(last, w.terms, sizeof(last), hipMemcpyDeviceToHost, ex), "terms read");
+  HIP_TRY(hipStreamSynchronize(ex), "sync");
   rep->final_loss = last[QG_T_TOTAL];
   double tot;
   s = eval_score(&tot, rep->terms);
@@ -833,7 +849,9 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
     r->time_to_gap_s = -1.0;
     r->wall_s = wall;
     double last[QG_NTERMS];
-    HIP_TRY(hipMemcpy(last, w[i].terms, sizeof(last), hipMemcpyDeviceToHost), "terms read");
+    HIP_TRY(hipMemcpyAsync(last, w[i].terms, sizeof(last), hipMemcpyDeviceToHost, ex),
+            "terms read");
+    HIP_TRY(hipStreamSynchronize(ex), "sync");
     r->final_loss = last[QG_T_TOTAL];
     qg::EvalMode score{};
     score.schedule = 0;

@@ -107,6 +107,7 @@ struct DevWork {
   double* smaxp;       // [T][nLc]  per-chunk dL/dF of the worst contingency's own branch
   double* lamg; double* lamqg;   // [T][G] balance multipliers at each generator's bus
   double* isfk;        // [T][G16]  ISF[br(k*_t)][bus(j)] - rowsum/N of the period's worst outage
+  double* thr;         // [T][Lp]  test radius of the outage flows (k_ctg_pm)
 };
 
 // Offsets of the term partial sums inside DevWork::tpart.
@@ -119,7 +120,9 @@ struct CtgTile {
   int bl;   // branches per wavefront (8, 16 or 32)
   int wl;   // wavefronts per block, stacked along branches
   int tc;   // periods per block (the period range is split over grid.z)
-  int lt;   // consecutive tiles of wl * bl branches per block
+  int lt;   // consecutive tiles of wl * bl branches per block (split: of 8
+            // branches, shared by the block's wavefronts)
+  int split = 0;  // 1: period-split blocks (bl = 8, tc periods per wavefront)
 };
 
 // Homotopy source of one evaluation.
@@ -228,6 +231,7 @@ DevWork carve_workspace(const Problem* p, void* ws);
 int default_ctg_tc(const Problem& p, int wl);
 int default_ctg_lt(const Problem& p, const CtgTile& t);  // tiles per block for tile t
 void apply_ctg_tile(Problem* p, const CtgTile& t);        // set the tile and the l-block count
+CtgTile default_ctg_tile(const Problem& p);               // the tile a new problem starts with
 int ctg_tc_cap(int wl);  // most periods per block the LDS budget allows
 
 // Kernel launchers (qg_kernels.hip).  A step is kStages kernels.

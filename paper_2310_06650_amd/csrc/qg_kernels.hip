@@ -197,6 +197,23 @@ __device__ __forceinline__ R writelane_any(R v, R x, int lane) {
   return (int)(threadIdx.x & 63) == lane ? x : v;
 }
 
+// The same with v_writelane (one per 32-bit half), for lanes known at compile
+// time after unrolling (an immediate lane select, which also leaves the one
+// scalar operand the instruction may read to x): the select form would keep
+// one lane mask per constant live in SGPRs.
+__device__ __forceinline__ unsigned writelane_u32(unsigned v, unsigned x, int lane) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "i"(lane));
+  return v;
+}
+__device__ __forceinline__ double writelane_set(double v, double x, int lane) {
+  const unsigned lo = writelane_u32((unsigned)__double2loint(v), (unsigned)__double2loint(x), lane);
+  const unsigned hi = writelane_u32((unsigned)__double2hiint(v), (unsigned)__double2hiint(x), lane);
+  return __hiloint2double((int)hi, (int)lo);
+}
+__device__ __forceinline__ float writelane_set(float v, float x, int lane) {
+  return __uint_as_float(writelane_u32(__float_as_uint(v), __float_as_uint(x), lane));
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
@@ -527,7 +544,14 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
     // reactive part of the contingency flows: max(q_fr^2, q_to^2), ties: from
     const double qf2 = qf * qf, qt2 = qt * qt;
     const bool qfr = qf2 >= qt2;
-    w.q2[(size_t)t * p.Lp + l] = qfr ? qf2 : qt2;
+    const double qm2 = qfr ? qf2 : qt2;
+    w.q2[(size_t)t * p.Lp + l] = qm2;
+    // radius of the map-reduce's first test: with margins of 2^-40 on s_ctg^2
+    // and 2^-50 on the root, fl(P^2 + qmax2) > s_ctg^2 implies |P| > thr
+    // under FP64 rounding; -1 (every flow passes) where qmax2 alone comes
+    // within the margin of the rating
+    const double A = p.ctg_smax2[l] * (1.0 - 0x1p-40) - qm2;
+    w.thr[(size_t)t * p.Lp + l] = A > 0.0 ? sqrt(A) * (1.0 - 0x1p-50) : -1.0;
     const size_t TL = (size_t)T * L, e = (size_t)t * L + l;
     w.bco[0 * TL + e] = cs;
     w.bco[1 * TL + e] = sn;
@@ -663,7 +687,10 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
     w.tpart[a.toff.rsv + t] = krs * soft_relu(short_, eps);
     w.drs[t] = krs * soft_relu_d(short_, eps);
   }
-  for (int l = p.L + tid; l < p.Lp; l += kBlock) w.q2[(size_t)t * p.Lp + l] = 0.0;
+  for (int l = p.L + tid; l < p.Lp; l += kBlock) {
+    w.q2[(size_t)t * p.Lp + l] = 0.0;
+    w.thr[(size_t)t * p.Lp + l] = -1.0;
+  }
   for (int k = p.K + tid; k < p.Kp; k += kBlock) w.Fk[(size_t)t * p.Kp + k] = 0.0;
 }
 
@@ -933,6 +960,180 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
     const size_t o = ((size_t)lb * T + t0 + tt) * Kp + kb * 64 + kk;
     w.zpart[o] = z;
     w.spart[o] = s2;
+  }
+}
+
+// Period-split form of the same map-reduce.  The wavefronts of a block share
+// one range of lt * 8 branches and split the periods: wavefront w owns the
+// periods [t0 + w TCW, t0 + (w + 1) TCW), so z_tk and S_tk of its lanes need
+// no sum over wavefronts and stay in registers over the whole branch range,
+// and with wl * TCW >= T every outage factor is read from memory once per
+// evaluation (the block's wavefronts read the same tile, served by the L1
+// cache).  Per period the eight tests of a tile are combined before one
+// ballot; a period with a flagged lane takes the per-branch path of
+// k_ctg_main.
+//
+// FP64: the test is |P| > thr_tl with thr_tl from k_forward, a radius a
+// little below sqrt(s_ctg^2 - qmax2_tl), so that every element the exact
+// test P^2 + qmax2 > s_ctg^2 accepts passes it (one FMA and one compare per
+// element); the exact test is applied again on the per-branch path.  F_tl
+// and thr_tl reach SGPRs by scalar loads issued one period ahead.  FP32
+// arithmetic keeps the exact test with F and qmax2 moved to SGPRs by
+// v_readlane from a per-tile lane load (lane e: period e / 8, branch e % 8).
+template <int TCW, typename LT>
+__global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
+  typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
+  constexpr bool kF64 = std::is_same<R, double>::value;
+  const DevProblem& p = a.p;
+  const DevWork& w = a.w;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int WL = blockDim.x >> 6;
+  const int lb = blockIdx.x, kb = blockIdx.y;
+  const int T = p.T, Lp = p.Lp, Kp = p.Kp;
+  const int tw = (blockIdx.z * WL + wv) * TCW;  // first period of the wavefront
+  const int ntw = min(TCW, T - tw);
+  if (ntw <= 0) return;  // no barrier follows
+  const int k = kb * 64 + lane;  // slot of the lane
+  const int kc = a.act_k ? a.act_k[k] : k;
+  // z and S of the wavefront's (period, lane) pairs live in its own slice
+  // of LDS: only the per-branch path and the final store touch them
+  extern __shared__ double dyn[];
+  double* zsh = dyn + (size_t)wv * TCW * 128;
+  double* ssh = zsh + TCW * 64;
+  R fk[TCW];
+#pragma unroll
+  for (int i = 0; i < TCW; ++i) {
+    fk[i] = i < ntw ? (R)w.Fk[(size_t)(tw + i) * Kp + kc] : R(0);
+    zsh[i * 64 + lane] = 0.0;
+    ssh[i * 64 + lane] = 0.0;
+  }
+  const cdouble* Sc = as_const(p.ctg_smax2);
+  const cdouble* Mc = as_const(p.ctg_smax);
+  const cdouble* Dc = as_const(p.dt);
+  const cdouble* Fc = as_const(w.F);
+  const cdouble* Qc = as_const(w.q2);
+  const cdouble* Hc = as_const(w.thr);
+  const double beta = w.params[PB_BETA];
+  const R eps = (R)w.params[PB_EPS];
+  const R eps2 = eps * eps;
+  const int ei = lane >> 3, eg = lane & 7;
+  const int l0 = lb * a.lt * 8;
+  const int l1 = min(Lp, l0 + a.lt * 8);
+  // FP64: F and thr of the next (period, tile) to be tested
+  double Fn[8], Hn[8];
+  if constexpr (kF64) {
+    const size_t e = (size_t)tw * Lp + min(l0, Lp - 8);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      Fn[g] = Fc[e + g];
+      Hn[g] = Hc[e + g];
+    }
+  }
+  for (int lbase = l0; lbase < l1; lbase += 8) {
+    R lod[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
+    R fv = R(0), qv = R(0), smx2[8];
+    if constexpr (!kF64) {
+      if (ei < ntw) {
+        const size_t e = (size_t)(tw + ei) * Lp + lbase + eg;
+        fv = (R)w.F[e];
+        qv = (R)w.q2[e];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) smx2[j] = (R)Sc[lbase + j];
+    }
+    // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
+    R racc = R(0), qacc = R(0);
+#pragma unroll
+    for (int i = 0; i < TCW; ++i) {
+      if (i < ntw) {
+        // lanes flagged by any of the eight tests (a ballot per test keeps
+        // the combination in SGPRs)
+        uint64_t hot = 0;
+        R Fr[8];
+        if constexpr (kF64) {
+          double Hr[8];
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            Fr[g] = Fn[g];
+            Hr[g] = Hn[g];
+          }
+          // prefetch: the next period of this tile, else period tw of the
+          // next tile (clamped to valid rows at the end)
+          const bool last = i + 1 >= ntw;
+          const int tn = last ? tw : tw + i + 1;
+          const int ln = last ? min(lbase + 8, Lp - 8) : lbase;
+          const size_t e = (size_t)tn * Lp + ln;
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            Fn[g] = Fc[e + g];
+            Hn[g] = Hc[e + g];
+          }
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            const double P = fma_uniform_c(lod[g], fk[i], Fr[g]);
+            hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+          }
+        } else {
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            Fr[g] = readlane_any(fv, i * 8 + g);
+            const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
+            const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
+            hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+          }
+        }
+        if (hot) {
+          const R kt = (R)(Dc[tw + i] * p.c_s * beta);
+          R Qr[8], Sr[8];
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            if constexpr (kF64) {
+              Qr[g] = Qc[(size_t)(tw + i) * Lp + lbase + g];
+              Sr[g] = Sc[lbase + g];
+            } else {
+              Qr[g] = readlane_any(qv, i * 8 + g);
+              Sr[g] = smx2[g];
+            }
+          }
+          R zt = R(0), st = R(0);
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            // the flow formed again (the same fused operation, so the same
+            // value): nothing of the test stays live across the branch
+            const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
+            const R s2 = fma(P, P, Qr[g]);
+            if (__builtin_amdgcn_ballot_w64(s2 > Sr[g])) {
+              R dP = R(0), dq = R(0);
+              if (s2 > Sr[g]) {
+                zt += ctg_overload(P, s2, (R)Mc[lbase + g], eps, eps2, kt, dP, dq);
+                st = fma(lod[g], dP, st);
+              }
+              const R r = pair_sum(dP, dq);  // lane 0: sum of dP, lane 32: of dq
+              racc = writelane_set(racc, readlane_any(r, 0), i * 8 + g);
+              qacc = writelane_set(qacc, readlane_any(r, 32), i * 8 + g);
+            }
+          }
+          zsh[i * 64 + lane] += (double)zt;
+          ssh[i * 64 + lane] += (double)st;
+        }
+      }
+    }
+    if (lane < ntw * 8) {
+      const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
+      w.rpart[o] = (double)racc;
+      w.qpart[o] = (double)qacc;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TCW; ++i) {
+    if (i < ntw) {
+      const size_t o = ((size_t)lb * T + tw + i) * Kp + k;
+      w.zpart[o] = zsh[i * 64 + lane];
+      w.spart[o] = ssh[i * 64 + lane];
+    }
   }
 }
 
@@ -1389,6 +1590,39 @@ void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArg
   }
 }
 
+template <int TCW, typename LT>
+void launch_ctg_pm_t(dim3 grid, dim3 block, hipStream_t s, const EvalArgs& a, const LT* lodf) {
+  // z and S of every (wavefront, period, lane)
+  const size_t lds = (size_t)(block.x / 64) * TCW * 128 * sizeof(double);
+  hipLaunchKernelGGL((k_ctg_pm<TCW, LT>), grid, block, lds, s, a, lodf);
+}
+
+template <typename LT>
+void launch_ctg_pm(int tcw, dim3 grid, dim3 block, hipStream_t s, const EvalArgs& a,
+                   const LT* lodf) {
+  switch (tcw) {
+    case 1: launch_ctg_pm_t<1>(grid, block, s, a, lodf); break;
+    case 2: launch_ctg_pm_t<2>(grid, block, s, a, lodf); break;
+    case 3: launch_ctg_pm_t<3>(grid, block, s, a, lodf); break;
+    case 4: launch_ctg_pm_t<4>(grid, block, s, a, lodf); break;
+    case 5: launch_ctg_pm_t<5>(grid, block, s, a, lodf); break;
+    case 6: launch_ctg_pm_t<6>(grid, block, s, a, lodf); break;
+    case 7: launch_ctg_pm_t<7>(grid, block, s, a, lodf); break;
+    default: launch_ctg_pm_t<8>(grid, block, s, a, lodf); break;
+  }
+}
+
+template <typename LT>
+void launch_ctg(const Problem* pr, hipStream_t s, const EvalArgs& a, const LT* lodf) {
+  const CtgTile& t = pr->tile;
+  const int span = t.split ? t.wl * t.tc : t.tc;
+  const dim3 grid(pr->nLb, a.nKb, (pr->T + span - 1) / span), block(64 * t.wl);
+  if (t.split)
+    launch_ctg_pm(t.tc, grid, block, s, a, lodf);
+  else
+    launch_ctg_main(t.bl, grid, block, s, a, lodf);
+}
+
 static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, double* grad,
                           double* terms_out, const EvalMode& mode, int fuse_adam, double* m,
                           double* v) {
@@ -1442,15 +1676,13 @@ static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStr
       break;
     case 1:
       if (pr->K > 0) {
-        const int ntc = (pr->T + pr->tile.tc - 1) / pr->tile.tc;
-        const dim3 grid(pr->nLb, a.nKb, ntc), block(64 * pr->tile.wl);
         const int kind = pr->dp.lodf_kind;
         if (kind == kLodfF64)
-          launch_ctg_main(pr->tile.bl, grid, block, s, a, static_cast<const double*>(a.lodf_sel));
+          launch_ctg(pr, s, a, static_cast<const double*>(a.lodf_sel));
         else if (kind == kLodfF32)
-          launch_ctg_main(pr->tile.bl, grid, block, s, a, static_cast<const float*>(a.lodf_sel));
+          launch_ctg(pr, s, a, static_cast<const float*>(a.lodf_sel));
         else
-          launch_ctg_main(pr->tile.bl, grid, block, s, a, static_cast<const uint16_t*>(a.lodf_sel));
+          launch_ctg(pr, s, a, static_cast<const uint16_t*>(a.lodf_sel));
       }
       break;
     case 2:

@@ -141,6 +141,7 @@ _sig = {
                                 _vp, C.POINTER(C.c_double)]),
     "qg_set_ctg_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "qg_set_ctg_ltiles": (C.c_int, [_vp, C.c_int32]),
+    "qg_set_ctg_tile_split": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "qg_eval_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp, _vp]),
     "qg_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double * QG_NCLASS,
                                C.POINTER(qg_adam_cfg), _vp]),
@@ -268,10 +269,10 @@ def qg_ctg_list(h, k):
 
 
 def qg_problem_dims(h):
-    out = np.zeros(18, dtype=np.int32)
-    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 18), "qg_problem_dims")
+    out = np.zeros(19, dtype=np.int32)
+    _check(lib.qg_problem_dims(h, out.ctypes.data_as(_pi), 19), "qg_problem_dims")
     keys = ("N", "L", "G", "T", "M", "K", "Lp", "Kp", "G16", "G4", "Tp", "nLb", "nKb",
-            "ctg_bl", "ctg_wl", "ctg_tc", "lodf_kind", "ctg_lt")
+            "ctg_bl", "ctg_wl", "ctg_tc", "lodf_kind", "ctg_lt", "ctg_split")
     return dict(zip(keys, (int(v) for v in out)))
 
 
@@ -374,6 +375,33 @@ class Problem:
         if lt is not None:
             _check(lib.qg_set_ctg_ltiles(self.handle, int(lt)), "qg_set_ctg_ltiles")
         self.dims = qg_problem_dims(self.handle)
+
+    def set_ctg_ltiles(self, lt):
+        _check(lib.qg_set_ctg_ltiles(self.handle, int(lt)), "qg_set_ctg_ltiles")
+        self.dims = qg_problem_dims(self.handle)
+
+    def set_ctg_tile_split(self, wl, tcw, lt=0):
+        _check(lib.qg_set_ctg_tile_split(self.handle, int(wl), int(tcw), int(lt)),
+               "qg_set_ctg_tile_split")
+        self.dims = qg_problem_dims(self.handle)
+
+    def tile(self):
+        """The map-reduce tile as text: "s{wl}x{tcw}x{lt}" for a period-split
+        tile, "{bl}x{wl}x{tc}x{lt}" for a branch-stacked one."""
+        d = self.dims
+        if d["ctg_split"]:
+            return f"s{d['ctg_wl']}x{d['ctg_tc']}x{d['ctg_lt']}"
+        return f"{d['ctg_bl']}x{d['ctg_wl']}x{d['ctg_tc']}x{d['ctg_lt']}"
+
+    def set_tile(self, text):
+        """Set a tile given in the text form of tile(); lt may be left out or
+        0 (the default)."""
+        if text.startswith("s"):
+            v = [int(u) for u in text[1:].split("x")]
+            self.set_ctg_tile_split(v[0], v[1], v[2] if len(v) > 2 else 0)
+        else:
+            v = [int(u) for u in text.split("x")]
+            self.set_ctg_tile(v[0], v[1], v[2], lt=(v[3] if len(v) > 3 else None))
 
     def new_vector(self, host=None):
         t = self.torch.zeros(self.n_x, dtype=self.torch.float64, device=self.device)
