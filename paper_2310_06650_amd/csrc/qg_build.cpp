@@ -174,7 +174,9 @@ WorkLayout work_layout(const Problem& p) {
       T * (size_t)p.nLc * D,                            // smaxp
       T * G * D, T * G * D,                             // lamg, lamqg
       T * (size_t)p.G16 * D,                            // isfk
-      T * p.Lp * D};                                    // thr
+      T * p.Lp * D,                                     // thr
+      T * (size_t)p.nKb_max * p.nLb_max,                // zflag
+      T * (size_t)(p.Lp / 8) * rflag_stride(p.nKb_max)};  // rflag
   WorkLayout w;
   const int n = (int)(sizeof(cnt) / sizeof(cnt[0]));
   size_t o = 0;
@@ -219,13 +221,21 @@ int default_ctg_lt(const Problem& p, const CtgTile& t) {
 }
 
 CtgTile default_ctg_tile(const Problem& p) {
-  // period-split blocks of four wavefronts, two periods per wavefront below
-  // 32 periods and four from there (measured on 4- to 48-period grids, every
-  // factor storage: 10-15 % faster than the best branch-stacked tile at 18
-  // periods, twice as fast at 48), branch tiles per block by the rule of
-  // default_ctg_lt
-  CtgTile t{8, 4, p.T >= 32 ? 4 : 2, 2};
-  t.split = 1;
+  // From 32 periods: period-split blocks of four wavefronts with four
+  // periods each (at 48 periods the map-reduce takes half the time of the
+  // best branch-stacked tile and the step 35 % less).  Below, 8 x 8
+  // branch-stacked blocks: at 18 periods the split form's map-reduce is a
+  // little faster, but its four times as many per-(period, contingency)
+  // partial sums cost more in the reduction that follows, and the whole step
+  // is 10 % slower.  Branch tiles per block by the rule of default_ctg_lt.
+  if (p.T >= 32) {
+    CtgTile t{8, 4, 4, 2};
+    t.split = 1;
+    t.lt = default_ctg_lt(p, t);
+    return t;
+  }
+  CtgTile t{8, 8, 0, 1};
+  t.tc = default_ctg_tc(p, t.wl);
   t.lt = default_ctg_lt(p, t);
   return t;
 }
@@ -731,6 +741,8 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   w.drs = D(25); w.zmaxp = D(26); w.zargp = D(27); w.zsump = D(28); w.kstar = D(29);
   w.smaxp = D(30);
   w.lamg = D(31); w.lamqg = D(32); w.isfk = D(33); w.thr = D(34);
+  w.zflag = base + wl.off[35];
+  w.rflag = base + wl.off[36];
   return w;
 }
 

@@ -108,7 +108,13 @@ struct DevWork {
   double* lamg; double* lamqg;   // [T][G] balance multipliers at each generator's bus
   double* isfk;        // [T][G16]  ISF[br(k*_t)][bus(j)] - rowsum/N of the period's worst outage
   double* thr;         // [T][Lp]  test radius of the outage flows (k_ctg_pm)
+  // which partials were stored (the rest are all zero and not written):
+  uint8_t* zflag;      // [T][nKb_max][nLb_max] z/S partials of (t, k-block, l-block)
+  uint8_t* rflag;      // [T][Lp/8][rflag_stride] R/Q partials of (t, 8 branches, k-block)
 };
+
+// Row stride of DevWork::rflag: k-blocks rounded up to 16 (16-byte loads).
+inline int rflag_stride(int nKb_max) { return (nKb_max + 15) / 16 * 16; }
 
 // Offsets of the term partial sums inside DevWork::tpart.
 struct TermOffsets {

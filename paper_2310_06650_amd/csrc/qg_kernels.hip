@@ -51,6 +51,9 @@ struct EvalArgs {
   int fuse_adam;
   int nb_br, nb_bus, bus_chunks, nb_gen, nsplit;
   int nLb, nKb, nKc, nLc, tc, lt;
+  // partials stored sparsely with flags (the period-split map-reduce);
+  // strides of w.zflag (k-blocks, l-blocks per row) and w.rflag (k-blocks)
+  int sparse, zfk, zfs, rfs;
   TermOffsets toff;
   // contingencies scored this step (Alg. 2): slot s of the map-reduce holds
   // contingency act_k[s] (the identity when act_k is null), na slots in use,
@@ -1121,7 +1124,12 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
         }
       }
     }
-    if (lane < ntw * 8) {
+    // per (period, 8 branches): stored only when not all zero, and flagged
+    const uint64_t b = __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0));
+    if (lane < ntw)
+      w.rflag[((size_t)(tw + lane) * (Lp / 8) + lbase / 8) * a.rfs + kb] =
+          (uint8_t)(((b >> (8 * lane)) & 0xFF) != 0);
+    if (lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
       const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
       w.rpart[o] = (double)racc;
       w.qpart[o] = (double)qacc;
@@ -1130,9 +1138,15 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
   for (int i = 0; i < TCW; ++i) {
     if (i < ntw) {
-      const size_t o = ((size_t)lb * T + tw + i) * Kp + k;
-      w.zpart[o] = zsh[i * 64 + lane];
-      w.spart[o] = ssh[i * 64 + lane];
+      // stored only when not all zero, and flagged
+      const double z = zsh[i * 64 + lane], s2 = ssh[i * 64 + lane];
+      const bool nz = __builtin_amdgcn_ballot_w64(z != 0.0 || s2 != 0.0) != 0;
+      if (lane == 0) w.zflag[((size_t)(tw + i) * a.zfk + kb) * a.zfs + lb] = (uint8_t)nz;
+      if (nz) {
+        const size_t o = ((size_t)lb * T + tw + i) * Kp + k;
+        w.zpart[o] = z;
+        w.spart[o] = s2;
+      }
     }
   }
 }
@@ -1153,8 +1167,37 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   const int s = kc * 64 + lane;  // slot
   const size_t o = (size_t)t * Kp + s;
   const size_t stride = (size_t)T * Kp;
-  const double zs = strided_sum<16>(w.zpart + o, a.nLb, stride);
-  const double ss = strided_sum<16>(w.spart + o, a.nLb, stride);
+  // the l-block partials in l-block order; after the period-split
+  // map-reduce only the flagged ones (the others are all zero), up to 16 of
+  // each in flight
+  double zs = 0.0, ss = 0.0;
+  if (!a.sparse) {
+    zs = strided_sum<16>(w.zpart + o, a.nLb, stride);
+    ss = strided_sum<16>(w.spart + o, a.nLb, stride);
+  }
+  const uint8_t* zf = w.zflag + ((size_t)t * a.zfk + kc) * a.zfs;
+  for (int b0 = 0; a.sparse && b0 < a.nLb; b0 += 64) {
+    uint64_t m = __builtin_amdgcn_ballot_w64(b0 + lane < a.nLb && zf[b0 + lane] != 0);
+    while (m) {
+      int idx[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        idx[u] = m ? b0 + __builtin_ctzll(m) : -1;
+        m &= m - 1;
+      }
+      double vz[16], vs[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        vz[u] = idx[u] >= 0 ? w.zpart[o + (size_t)idx[u] * stride] : 0.0;
+        vs[u] = idx[u] >= 0 ? w.spart[o + (size_t)idx[u] * stride] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        zs += vz[u];
+        ss += vs[u];
+      }
+    }
+  }
   double z = -DBL_MAX, zsum = 0.0;
   int idx = INT_MAX;
   if (s < a.na) {
@@ -1221,12 +1264,19 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
       ci = (int)w.zargp[ob + lane];
       cs = w.zsump[ob + lane];
     }
+    // after the period-split map-reduce only the flagged k-block partials
+    // were stored (the others are zero): the flags of the branch's group of
+    // 8 first, 16 k-blocks per load
     const size_t st = (size_t)T * Lp;
+    const uint8_t* rf = w.rflag + ((size_t)t * (Lp / 8) + l / 8) * a.rfs;
     for (int c0 = 0; c0 < a.nKb; c0 += 16) {
+      uint4 f4 = make_uint4(~0u, ~0u, ~0u, ~0u);
+      if (a.sparse) f4 = hasl ? *reinterpret_cast<const uint4*>(rf + c0) : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t fw[4] = {f4.x, f4.y, f4.z, f4.w};
       double vr[16], vq[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const bool ib = hasl && c0 + u < a.nKb;
+        const bool ib = hasl && c0 + u < a.nKb && ((fw[u >> 2] >> (8 * (u & 3))) & 0xFFu) != 0;
         vr[u] = ib ? w.rpart[o + (size_t)(c0 + u) * st] : 0.0;
         vq[u] = ib ? w.qpart[o + (size_t)(c0 + u) * st] : 0.0;
       }
@@ -1647,6 +1697,10 @@ static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, 
   a.nLc = pr->nLc;
   a.tc = pr->tile.tc;
   a.lt = pr->tile.lt;
+  a.sparse = pr->tile.split;
+  a.zfk = pr->nKb_max;
+  a.zfs = pr->nLb_max;
+  a.rfs = rflag_stride(pr->nKb_max);
   a.toff = pr->toff;
   const Screen& sc = pr->scr;
   if (mode.screened) {

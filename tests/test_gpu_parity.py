@@ -193,7 +193,7 @@ def test_ctg_split_tile_invariance(qg, wl, tcw, lt):
     oversized branch ranges."""
     c = case("c2")
     prob = qg.Problem(c)
-    assert prob.dims["ctg_split"] == 1          # the default form
+    assert prob.dims["ctg_split"] == 0          # the default below 32 periods
     x = synth.random_point(c, 10, spread=0.3)
     prob.set_ctg_tile(8, 8, 4, lt=1)
     assert prob.dims["ctg_split"] == 0
@@ -215,6 +215,7 @@ def test_ctg_split_tile_reduced_precision_matches_stacked(qg, flag):
     c = case("c2")
     prob = qg.Problem(c, flags=getattr(qg, flag))
     x = synth.random_point(c, 11, spread=0.3)
+    prob.set_ctg_tile_split(4, 2)
     t1, g1 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
     prob.set_ctg_tile(8, 8, 4, lt=1)
     t0, g0 = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
@@ -230,6 +231,7 @@ def test_ctg_split_tiles_c3_against_oracle(qg):
     tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
     for tile in (None, (8, 6, 8)):
         prob = qg.Problem(c)
+        assert prob.dims["ctg_split"] == 1      # the default from 32 periods
         if tile:
             prob.set_ctg_tile_split(*tile)
         t, g = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)

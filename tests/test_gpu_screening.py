@@ -86,13 +86,17 @@ def gpu_eval(prob, x, eps, beta, rho):
     return t.cpu().numpy(), g.cpu().numpy()
 
 
-@pytest.mark.parametrize("name,n_act,seed", [("c1", 5, 1), ("c2", 100, 2), ("c2", 64, 3),
-                                             ("c2", 1, 4), ("c3", 300, 5)])
-def test_given_set_matches_oracle(qg, name, n_act, seed):
+@pytest.mark.parametrize("name,n_act,seed,tile", [("c1", 5, 1, None), ("c2", 100, 2, None),
+                                                  ("c2", 100, 2, "s4x2x3"), ("c2", 64, 3, None),
+                                                  ("c2", 1, 4, "s2x3"), ("c2", 1, 4, None),
+                                                  ("c3", 300, 5, None), ("c3", 300, 5, "8x8x7x4")])
+def test_given_set_matches_oracle(qg, name, n_act, seed, tile):
     """Sets spanning several 64-slot chunks with a ragged tail, one slot, and
-    the 2,410-contingency grid."""
+    the 2,410-contingency grid, under both tile forms."""
     c = case(name)
     prob = qg.Problem(c)
+    if tile:
+        prob.set_tile(tile)
     K = prob.K
     prob.set_screening(top_frac=n_act / K, rand_frac=0.0)
     rng = np.random.default_rng(seed)
@@ -111,6 +115,7 @@ def test_given_set_reduced_precision(qg, prec):
     c = case("c2")
     flags = qg.QG_FLAG_CTG_FP32 if prec == "fp32" else qg.QG_FLAG_CTG_BF16
     prob = qg.Problem(c, flags=flags)
+    prob.set_tile("s4x2")
     prob.set_screening(top_frac=0.2, rand_frac=0.0)
     A = np.sort(np.random.default_rng(8).choice(prob.K, size=prob.K // 5, replace=False))
     prob.set_active_contingencies(A)
