@@ -824,6 +824,7 @@ template <int BL, typename LT>
 __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restrict__ lodf) {
   static_assert(BL % 8 == 0 && BL <= 32, "branches per wavefront");
   typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
+  constexpr bool kF64 = std::is_same<R, double>::value;
   // LDS: sFk[TC][64] (outaged branches' flows), then per period and
   // wavefront the lanes' z and S: zsh[TC][WL][64], ssh[TC][WL][64]
   extern __shared__ double dyn[];
@@ -857,9 +858,9 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
     const int lbase = __builtin_amdgcn_readfirstlane((lb * a.lt + it) * BL * WL + wv * BL);
     const bool on = lbase < Lp;
     R lod[BL], smx2[BL];
-    // lane e of chunk c holds F and qmax2 of period t0 + e / 8, branch
-    // lbase + 8 c + e % 8 (TC * 8 <= 64 entries)
-    R fv[BL / 8], qv[BL / 8];
+    // lane e of chunk c holds F, qmax2 and (FP64) the test radius thr of
+    // period t0 + e / 8, branch lbase + 8 c + e % 8 (TC * 8 <= 64 entries)
+    R fv[BL / 8], qv[BL / 8], hv[BL / 8];
     if (on) {
 #pragma unroll
       for (int j = 0; j < BL; ++j) {
@@ -871,10 +872,12 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
       for (int c = 0; c < BL / 8; ++c) {
         fv[c] = R(0);
         qv[c] = R(0);
+        hv[c] = R(0);
         if (et < nt) {
           const size_t e = (size_t)(t0 + et) * Lp + lbase + c * 8 + eg;
           fv[c] = (R)w.F[e];
           qv[c] = (R)w.q2[e];
+          if constexpr (kF64) hv[c] = w.thr[e];
         }
       }
     }
@@ -896,18 +899,30 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
 #pragma unroll
         for (int c = 0; c < BL / 8; ++c) {
           R Fr[8], Qr[8], P[8];
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            Fr[g] = readlane_any(fv[c], tt * 8 + g);
-            Qr[g] = readlane_any(qv[c], tt * 8 + g);
-          }
           unsigned rows = 0;
+          if constexpr (kF64) {
+            // FP64: |P| > thr, which every element of the exact test passes
+            // (the radius of k_forward); the exact test follows per branch
 #pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            const int j = c * 8 + g;
-            P[g] = fma_uniform_c(lod[j], fk, Fr[g]);
-            const R s2 = fma_uniform_c(P[g], P[g], Qr[g]);
-            if (__builtin_amdgcn_ballot_w64(s2 > smx2[j])) rows |= 1u << g;
+            for (int g = 0; g < 8; ++g) {
+              Fr[g] = readlane_any(fv[c], tt * 8 + g);
+              const R Hr = readlane_any(hv[c], tt * 8 + g);
+              P[g] = fma_uniform_c(lod[c * 8 + g], fk, Fr[g]);
+              if (__builtin_amdgcn_ballot_w64(fabs(P[g]) > Hr)) rows |= 1u << g;
+            }
+          } else {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              Fr[g] = readlane_any(fv[c], tt * 8 + g);
+              Qr[g] = readlane_any(qv[c], tt * 8 + g);
+            }
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              const int j = c * 8 + g;
+              P[g] = fma_uniform_c(lod[j], fk, Fr[g]);
+              const R s2 = fma_uniform_c(P[g], P[g], Qr[g]);
+              if (__builtin_amdgcn_ballot_w64(s2 > smx2[j])) rows |= 1u << g;
+            }
           }
           if (rows) {
             const R kt = (R)(Dc[t] * p.c_s * beta);
@@ -915,6 +930,7 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
             for (int g = 0; g < 8; ++g) {
               if ((rows >> g) & 1u) {
                 const int j = c * 8 + g;
+                if constexpr (kF64) Qr[g] = readlane_any(qv[c], tt * 8 + g);
                 // the square is formed again (the same fused operation, so
                 // the same value) rather than kept across the test of all
                 // eight branches: fewer live registers
@@ -1157,6 +1173,7 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 // chunk the worst penalty (smallest index on ties) and the sum.  One 64-thread
 // block per (chunk, t); all partial loads of a lane are in flight together.
 
+template <bool SPARSE>
 __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
@@ -1171,12 +1188,12 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   // map-reduce only the flagged ones (the others are all zero), up to 16 of
   // each in flight
   double zs = 0.0, ss = 0.0;
-  if (!a.sparse) {
+  if constexpr (!SPARSE) {
     zs = strided_sum<16>(w.zpart + o, a.nLb, stride);
     ss = strided_sum<16>(w.spart + o, a.nLb, stride);
   }
   const uint8_t* zf = w.zflag + ((size_t)t * a.zfk + kc) * a.zfs;
-  for (int b0 = 0; a.sparse && b0 < a.nLb; b0 += 64) {
+  for (int b0 = 0; SPARSE && b0 < a.nLb; b0 += 64) {
     uint64_t m = __builtin_amdgcn_ballot_w64(b0 + lane < a.nLb && zf[b0 + lane] != 0);
     while (m) {
       int idx[16];
@@ -1226,6 +1243,7 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
 // outage-correction term S* = sum_l LODF_lk* dP_tlk* belongs to dL/dF at the
 // outaged branch and is applied in k_final as a rank-1 term (per-chunk sums).
 
+template <bool SPARSE>
 __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
@@ -1271,7 +1289,8 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
     const uint8_t* rf = w.rflag + ((size_t)t * (Lp / 8) + l / 8) * a.rfs;
     for (int c0 = 0; c0 < a.nKb; c0 += 16) {
       uint4 f4 = make_uint4(~0u, ~0u, ~0u, ~0u);
-      if (a.sparse) f4 = hasl ? *reinterpret_cast<const uint4*>(rf + c0) : make_uint4(0u, 0u, 0u, 0u);
+      if constexpr (SPARSE)
+        f4 = hasl ? *reinterpret_cast<const uint4*>(rf + c0) : make_uint4(0u, 0u, 0u, 0u);
       const uint32_t fw[4] = {f4.x, f4.y, f4.z, f4.w};
       double vr[16], vq[16];
 #pragma unroll
@@ -1344,11 +1363,12 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
 
 // Blocks [0, nLc T): flow adjoints of (period, 256-branch chunk); then the
 // nb_bus power-balance blocks, which only need the forward flows.
+template <bool SPARSE>
 __global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
   __shared__ double smem[2 * kSegChunk + 16];
   const int b = blockIdx.x, nasm = a.nLc * a.p.T;
   if (b < nasm)
-    ctg_assemble(a, b / a.nLc, b % a.nLc, smem);
+    ctg_assemble<SPARSE>(a, b / a.nLc, b % a.nLc, smem);
   else
     bus_balance(a, b - nasm, smem);
 }
@@ -1740,10 +1760,20 @@ static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStr
       }
       break;
     case 2:
-      if (pr->K > 0) hipLaunchKernelGGL(k_ctg_zred, dim3(a.nKc, pr->T), dim3(64), 0, s, a);
+      if (pr->K > 0) {
+        if (a.sparse)
+          hipLaunchKernelGGL(k_ctg_zred<true>, dim3(a.nKc, pr->T), dim3(64), 0, s, a);
+        else
+          hipLaunchKernelGGL(k_ctg_zred<false>, dim3(a.nKc, pr->T), dim3(64), 0, s, a);
+      }
       break;
     case 3:
-      hipLaunchKernelGGL(k_ctg_asm, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0, s, a);
+      if (a.sparse)
+        hipLaunchKernelGGL(k_ctg_asm<true>, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0,
+                           s, a);
+      else
+        hipLaunchKernelGGL(k_ctg_asm<false>, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0,
+                           s, a);
       break;
     case 4:
       hipLaunchKernelGGL(k_adjoint,
