@@ -8,6 +8,7 @@
 //                     F_t = ISF[:, gen] p_t - ISF load_t - mean_t ISF 1 (uniform slack)
 //   k_ctg_main      per-(t, l, k) outage flows F_l + LODF_lk F_k, their (eqs. (rank_correct),
 //                     penalties and partial reductions                   (sfr_pen)-(zctg), (2nd_lin_sys))
+//                     (k_ctg_pm: the same stage with period-split blocks)
 //   k_ctg_zred      per-(t, k) penalties z_tk, per-chunk worst and sum
 //   k_ctg_asm       per-(t, l) dL/dF and dL/dqmax2 (mean + worst-contingency weights)
 //                   + per-(t, bus) power balance from bus-sorted endpoint flows
@@ -985,12 +986,14 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
 // Period-split form of the same map-reduce.  The wavefronts of a block share
 // one range of lt * 8 branches and split the periods: wavefront w owns the
 // periods [t0 + w TCW, t0 + (w + 1) TCW), so z_tk and S_tk of its lanes need
-// no sum over wavefronts and stay in registers over the whole branch range,
-// and with wl * TCW >= T every outage factor is read from memory once per
-// evaluation (the block's wavefronts read the same tile, served by the L1
-// cache).  Per period the eight tests of a tile are combined before one
-// ballot; a period with a flagged lane takes the per-branch path of
-// k_ctg_main.
+// no sum over wavefronts and stay with the wavefront (in its own LDS slice)
+// over the whole branch range, and with wl * TCW >= T every outage factor is
+// read from memory once per evaluation (the block's wavefronts read the same
+// tile, served by the L1 cache).  Per period the eight tests of a tile are
+// combined before one branch; a period with a flagged lane takes the
+// per-branch path of k_ctg_main.  A group of 64 z/S partials or of 8 R/Q
+// partials is stored only when not all zero, with a byte flag per group
+// (w.zflag, w.rflag) that the readers consult first.
 //
 // FP64: the test is |P| > thr_tl with thr_tl from k_forward, a radius a
 // little below sqrt(s_ctg^2 - qmax2_tl), so that every element the exact
