@@ -5,12 +5,14 @@ tiles per block; branch-stacked: branches per wavefront, wavefronts per
 block, periods per block, branch tiles per block) trades the re-reads of the
 outage factors, the partial sums and the per-block fixed costs against the
 number of blocks in flight; the best choice depends on the grid's shape.
-Tiles are named by their text form (``Problem.tile``).  ``tune`` times the
-three kernels the tile affects (map-reduce, per-contingency and per-branch
-reductions) for each candidate with qg_time_stage at a given point and keeps
-the fastest; results are cached per shape class (padded branch and
-contingency counts, periods, factor storage) in a JSON file
-($QG_AUTOTUNE_CACHE, default ~/.cache/qg/autotune.json).
+Tiles are named by their text form (``Problem.tile``).  ``tune`` times, for
+each candidate, a short graph-replayed solve from a copy of the given point
+(the whole step: the tile also changes how much the reductions after the
+map-reduce read, and the kernels' overlap) -- or, with measure="stages", the
+three kernels the tile affects with qg_time_stage -- and keeps the fastest;
+results are cached per shape class (padded branch and contingency counts,
+periods, factor storage) in a JSON file ($QG_AUTOTUNE_CACHE, default
+~/.cache/qg/autotune.json).
 """
 from __future__ import annotations
 
@@ -54,26 +56,48 @@ def _save(cache):
         pass
 
 
-def tune(prob, x, reps=30, eps=1e-2, candidates=None, use_cache=True):
+def step_us(prob, x, steps=64, eps=1e-2):
+    """Microseconds per step of a graph-replayed solve of ``steps`` steps from
+    a copy of x (small fixed step sizes and homotopy), after one untimed solve
+    that captures the graph.  x itself is not changed."""
+    xs = x.clone()
+    m, v = prob.new_vector(), prob.new_vector()
+    opts = qg.solve_opts(steps, [1e-5] * qg.QG_NCLASS, n_total=steps, eps0=eps, epsf=eps,
+                         use_graph=1)
+    prob.solve(xs, m, v, opts)
+    xs.copy_(x)
+    m.zero_()
+    v.zero_()
+    rep = prob.solve(xs, m, v, opts)
+    return rep.wall_s / steps * 1e6
+
+
+def tune(prob, x, reps=30, eps=1e-2, candidates=None, use_cache=True, measure="step",
+         steps=64):
     """Set the fastest tile on prob (timed at the point x) and return
-    (tile, {tile: microseconds})."""
+    (tile, {tile: microseconds}): per step of a short solve (measure="step")
+    or the sum of the three contingency kernels (measure="stages", reps
+    launches each)."""
     key = shape_key(prob)
     cache = _load() if use_cache else {}
-    if use_cache and key in cache and isinstance(cache[key].get("tile"), str):
-        tile = cache[key]["tile"]
-        prob.set_tile(tile)
-        return tile, cache[key]["times"]
+    hit = cache.get(key)
+    if use_cache and hit and isinstance(hit.get("tile"), str) and hit.get("measure") == measure:
+        prob.set_tile(hit["tile"])
+        return hit["tile"], hit["times"]
     times = {}
     for cand in (candidates or CANDIDATES):
         try:
             prob.set_tile(cand)
         except qg.QgError:
             continue
-        us = sum(prob.time_stage(x, s, reps, eps) for s in (1, 2, 3))
+        if measure == "step":
+            us = step_us(prob, x, steps, eps)
+        else:
+            us = sum(prob.time_stage(x, s, reps, eps) for s in (1, 2, 3))
         times[prob.tile()] = us
     tile = min(times, key=times.get)
     prob.set_tile(tile)
     if use_cache:
-        cache[key] = dict(tile=tile, times=times)
+        cache[key] = dict(tile=tile, times=times, measure=measure)
         _save(cache)
     return tile, times

@@ -40,7 +40,7 @@ def main():
         if args.no_tune:
             tiles.append(None)
             continue
-        tile, _ = autotune.tune(p, p.new_vector(x0))
+        tile, _ = autotune.tune(p, p.new_vector(x0), steps=32)
         tiles.append(tile)
     tune_s = time.perf_counter() - t0
     opts = qg.solve_opts(args.steps, [3e-3] * 6, alphaf=[1e-5] * 6, n_total=args.steps,

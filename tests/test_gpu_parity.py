@@ -503,20 +503,27 @@ def test_batched_solve_matches_single_solves(qg):
 
 
 def test_autotuner_picks_a_timed_tile_and_caches_it(qg, tmp_path, monkeypatch):
+    import torch
     from paper_2310_06650_amd import autotune
     monkeypatch.setenv("QG_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     c = case("c2")
     prob = qg.Problem(c)
     x = prob.new_vector(synth.flat_start(c))
-    tile, times = autotune.tune(prob, x, reps=5)
+    x0 = x.clone()
+    tile, times = autotune.tune(prob, x, steps=16)
+    assert torch.equal(x, x0)                  # timed on a copy
     assert times and tile in times
     assert times[tile] == min(times.values())
     assert prob.tile() == tile
     # both tile forms were timed
     assert any(t.startswith("s") for t in times) and any(not t.startswith("s") for t in times)
     prob2 = qg.Problem(c)
-    tile2, times2 = autotune.tune(prob2, prob2.new_vector(synth.flat_start(c)), reps=5)
+    tile2, times2 = autotune.tune(prob2, prob2.new_vector(synth.flat_start(c)), steps=16)
     assert tile2 == tile and times2 == times   # from the cache
+    # the per-kernel measure (re-tuned: the cache entry records its measure)
+    tile3, times3 = autotune.tune(prob2, x, reps=5, measure="stages")
+    assert tile3 in times3 and times3[tile3] == min(times3.values())
+    assert prob2.tile() == tile3
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
