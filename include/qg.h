@@ -345,7 +345,7 @@ qg_status qg_set_ctg_tile_split(qg_problem* prob, int32_t wl, int32_t tcw, int32
  * workspace into host memory (synchronises the stream).  Names and shapes
  * (row-major, padded sizes from qg_problem_dims):
  *   "F" [T][Lp] base-case DC flows      "Fk" [T][Kp] flows of outaged branches
- *   "q2" [T][Lp] max(q_fr^2, q_to^2)
+ *   "q2" [T][Lp] max(q_fr^2, q_to^2)   "thr" [T][Lp] test radius of the outage flows
  *   "lamp", "lamq" [T][N] balance multipliers
  *   "zval" [T][Kp] contingency penalties z_tk
  *   "gfT" [Lp][Tp] dL/dF                "qtot" [T][Lp] dL/d max(q^2)

@@ -880,7 +880,7 @@ qg_status qg_debug_fetch(const qg_problem* pr, const void* d_workspace, const ch
   struct Item { const char* n; const void* ptr; size_t bytes; };
   const Item items[] = {
       {"F", w.F, (size_t)p.T * p.Lp * D},       {"Fk", w.Fk, (size_t)p.T * p.Kp * D},
-      {"q2", w.q2, (size_t)p.T * p.Lp * D},
+      {"q2", w.q2, (size_t)p.T * p.Lp * D},     {"thr", w.thr, (size_t)p.T * p.Lp * D},
       {"lamp", w.lamp, (size_t)p.T * p.N * D},  {"lamq", w.lamq, (size_t)p.T * p.N * D},
       {"zval", w.zval, (size_t)p.T * p.Kp * D}, {"gfT", w.gfT, (size_t)p.Lp * p.Tp * D},
       {"gpdc", w.gpdc, (size_t)p.nsplit * p.T * p.G16 * D},

@@ -240,6 +240,43 @@ def test_ctg_split_tiles_c3_against_oracle(qg):
         prob.close()
 
 
+def test_test_radius_keeps_every_overloaded_flow(qg):
+    """The FP64 prefilter |P| > thr of both map-reduce forms: for flows P
+    within 40 ulps of the boundary sqrt(s_ctg^2 - qmax2) (both signs), every
+    one the exact test fl(P^2 + qmax2) > s_ctg^2 accepts (the FMA rounded
+    once, emulated exactly with rationals) passes |P| > thr, with thr as the
+    forward kernel computed it; where qmax2 alone reaches the rating thr is
+    -1, and the padding branches carry -1."""
+    from fractions import Fraction
+    c = case("c2")
+    prob = qg.Problem(c)
+    x = synth.random_point(c, 12, spread=0.3)
+    gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
+    d = prob.dims
+    T, L, Lp = d["T"], d["L"], d["Lp"]
+    thr = prob.fetch("thr", (T, Lp))
+    q2 = prob.fetch("q2", (T, Lp))
+    s2 = np.asarray(c.br_smax_ctg, dtype=np.float64) ** 2
+    assert np.all(thr[:, L:] == -1.0)
+    A = s2[None, :] - q2[:, :L]
+    assert np.all(thr[:, :L][A <= 0.0] == -1.0)
+    rng = np.random.default_rng(3)
+    ts, ls = np.nonzero(A > 0.0)
+    pick = rng.choice(len(ts), size=min(150, len(ts)), replace=False)
+    checked = 0
+    for i in pick:
+        t, l = ts[i], ls[i]
+        S, Q, H = s2[l], q2[t, l], thr[t, l]
+        P = np.sqrt(S - Q) - 40 * np.spacing(np.sqrt(S - Q))
+        for _ in range(81):
+            exact = float(Fraction(float(P)) ** 2 + Fraction(float(Q))) > S
+            if exact:
+                assert abs(P) > H and abs(-P) > H
+                checked += 1
+            P = np.nextafter(P, np.inf)
+    assert checked > 1000
+
+
 def test_ctg_split_tile_arguments_rejected(qg):
     prob = qg.Problem(case("c1"))
     for wl, tcw, lt in ((0, 2, 2), (9, 2, 2), (4, 0, 2), (4, 9, 2), (4, 2, 1), (4, 2, 65),
