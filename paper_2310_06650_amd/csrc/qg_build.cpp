@@ -176,7 +176,8 @@ WorkLayout work_layout(const Problem& p) {
       T * (size_t)p.G16 * D,                            // isfk
       T * p.Lp * D,                                     // thr
       T * (size_t)p.nKb_max * p.nLb_max,                // zflag
-      T * (size_t)(p.Lp / 8) * rflag_stride(p.nKb_max)};  // rflag
+      T * (size_t)(p.Lp / 8) * rflag_stride(p.nKb_max),   // rflag
+      kSchedStride * D};                                // snext
   WorkLayout w;
   const int n = (int)(sizeof(cnt) / sizeof(cnt[0]));
   size_t o = 0;
@@ -743,6 +744,7 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   w.lamg = D(31); w.lamqg = D(32); w.isfk = D(33); w.thr = D(34);
   w.zflag = base + wl.off[35];
   w.rflag = base + wl.off[36];
+  w.snext = D(37);
   return w;
 }
 

@@ -82,6 +82,7 @@ struct DevWork {
   double* params;      // [kParams] parameters of the step being evaluated
   int64_t* step;       // [1] index of the current step in the schedule table
   double* sched;       // [kSchedCap][kSchedStride] per-step eps, beta, rho_s, alpha[6], bc1, bc2
+  double* snext;       // [kSchedStride] the schedule row of the next scheduled evaluation
   double* epP; double* epQ;      // [T][2L] branch flows at bus-sorted endpoint slots
   double* bco;         // [9][T][L] per-branch reverse coefficients
   double* q2;          // [T][Lp]  max(q_fr^2, q_to^2)

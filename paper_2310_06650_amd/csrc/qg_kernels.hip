@@ -347,7 +347,9 @@ __device__ void resolve_params(const EvalArgs& a, StepParams& sp) {
     sp.bc1 = sp.bc2 = 1.0;
     return;
   }
-  const double* row = a.w.sched + (size_t)a.w.step[0] * kSchedStride;
+  // the row of this step, copied ahead by the previous step (k_ctg_asm) or
+  // by k_set_step: one load instead of the counter and then the row
+  const double* row = a.w.snext;
   sp.eps = row[0];
   sp.beta = row[1];
   sp.rho_s = row[2];
@@ -1370,6 +1372,13 @@ template <bool SPARSE>
 __global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
   __shared__ double smem[2 * kSegChunk + 16];
   const int b = blockIdx.x, nasm = a.nLc * a.p.T;
+  // scheduled steps: the next step's schedule row (the counter is advanced
+  // by k_final, after this kernel), clamped to the table; a new table comes
+  // with k_set_step, which copies its own row
+  if (a.mode.schedule && b == (int)gridDim.x - 1 && threadIdx.x < kSchedStride) {
+    const int64_t s1 = min(a.w.step[0] + 1, (int64_t)kSchedCap - 1);
+    a.w.snext[threadIdx.x] = a.w.sched[s1 * kSchedStride + threadIdx.x];
+  }
   if (b < nasm)
     ctg_assemble<SPARSE>(a, b / a.nLc, b % a.nLc, smem);
   else
@@ -1635,8 +1644,10 @@ __global__ __launch_bounds__(kBlock) void k_adam(DevProblem p, double* x, double
   adam_entry(x, m, v, e, g[e], lr, lo, hi, ac);
 }
 
-__global__ void k_set_step(int64_t* step, int64_t value) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) step[0] = value;
+__global__ void k_set_step(int64_t* step, int64_t value, const double* sched, double* snext) {
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x == 0) step[0] = value;
+  if (threadIdx.x < kSchedStride) snext[threadIdx.x] = sched[value * kSchedStride + threadIdx.x];
 }
 
 __global__ void k_clear_flag(int* flag) {
@@ -1841,8 +1852,9 @@ int launch_adam(const Problem* pr, double* x, double* m, double* v, const double
 
 int launch_set_step(const Problem* pr, const DevWork& w, int64_t value, void* stream) {
   (void)pr;
+  if (value < 0 || value >= kSchedCap) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
-                     w.step, value);
+                     w.step, value, (const double*)w.sched, w.snext);
   return (int)hipGetLastError();
 }
 
