@@ -81,11 +81,6 @@ __device__ __forceinline__ double soft_relu_d(double e, double eps) {
   return m / sqrt(m * m + eps * eps);
 }
 
-__device__ __forceinline__ double soft_abs_d(double v, double eps) {
-  const double s = sqrt(v * v + eps * eps);
-  return s > 0.0 ? v / s : 0.0;
-}
-
 // 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps on
 // y^-2 = x (y <- y + y (1 - x y^2) / 2), which restores FP64 accuracy.
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -94,6 +89,22 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   y = fma(0.5 * y, r, y);
   r = fma(-x * y, y, 1.0);
   return fma(0.5 * y, r, y);
+}
+
+// sigma(e) = sqrt(max(e,0)^2 + eps^2) and d sigma/de = max(e,0)/sigma (0 where
+// max(e,0) = 0) from one reciprocal square root, for the per-generator
+// penalties: a dependent sqrt and division per term cost more than the
+// whole rest of a period block at 18 periods.  Both 0 when eps = 0 and e <= 0.
+__device__ __forceinline__ double soft_relu_pair(double e, double eps, double& d) {
+  const double m = fmax(e, 0.0);
+  const double x = fma(m, m, eps * eps);
+  if (!(x > 0.0)) {
+    d = 0.0;
+    return 0.0;
+  }
+  const double r = rsqrt_nr(x);
+  d = m * r;
+  return x * r;
 }
 
 template <int CTRL, int ROWS>
@@ -533,8 +544,9 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
     const bool use_f = sf >= st;
     const double eb = (use_f ? sf : st) - p.br_smax[l];
     const double kbr = p.dt[t] * p.c_s * sp.beta;
-    part[0] = kbr * soft_relu(eb, sp.eps);
-    const double kth = kbr * soft_relu_d(eb, sp.eps);
+    double kth;
+    part[0] = kbr * soft_relu_pair(eb, sp.eps, kth);
+    kth *= kbr;
     double kpf = 0.0, kqf = 0.0, kpt = 0.0, kqt = 0.0;
     if (use_f) {
       if (sf > 0.0) { kpf = kth * pf / sf; kqf = kth * qf / sf; }
@@ -544,9 +556,10 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
     // angle-difference penalty
     const double ea = fabs(d) - p.ang_max;
     const double kang = p.dt[t] * p.c_ang * sp.beta;
-    part[1] = kang * soft_relu(ea, sp.eps);
+    double ka;
+    part[1] = kang * soft_relu_pair(ea, sp.eps, ka);
     const double sgn = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
-    const double kd = kang * soft_relu_d(ea, sp.eps) * sgn;
+    const double kd = kang * ka * sgn;
     // reactive part of the contingency flows: max(q_fr^2, q_to^2), ties: from
     const double qf2 = qf * qf, qt2 = qt * qt;
     const bool qfr = qf2 >= qt2;
@@ -648,33 +661,36 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
     }
     double pen = 0.0, a_, dd;
     a_ = pj + rj - pmax * uj;                             // headroom
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gp += dd; gr += dd; gu -= dd * pmax;
     a_ = pmin * uj - pj;                                  // minimum output
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gu += dd * pmin; gp -= dd;
     a_ = pj - pm1 - dtt * (ru * uj + rusu * (1.0 - uj));  // ramp up
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gp += dd; gu -= dd * dtt * (ru - rusu);
     a_ = pm1 - pj - dtt * (rd * uj + rdsd * (1.0 - uj));  // ramp down
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gp -= dd; gu -= dd * dtt * (rd - rdsd);
     a_ = qj - qmax * uj;                                  // reactive upper
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gq += dd; gu -= dd * qmax;
     a_ = qmin * uj - qj;                                  // reactive lower
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gu += dd * qmin; gq -= dd;
     a_ = rj - rmax * uj;                                  // reserve capability
-    pen += soft_relu(a_, eps); dd = kpen * soft_relu_d(a_, eps);
+    pen += soft_relu_pair(a_, eps, dd); dd *= kpen;
     gr += dd; gu -= dd * rmax;
     if (nxt) {  // the next period's ramp constraints depend on p_t
       const double dt1 = p.dt[t + 1];
       const double k1 = sp.rho_s * p.rho * sp.beta * dt1;
       a_ = p1 - pj - dt1 * (ru * u1 + rusu * (1.0 - u1));
-      gp -= k1 * soft_relu_d(a_, eps);
+      double d1;
+      (void)soft_relu_pair(a_, eps, d1);
+      gp -= k1 * d1;
       a_ = pj - p1 - dt1 * (rd * u1 + rdsd * (1.0 - u1));
-      gp += k1 * soft_relu_d(a_, eps);
+      (void)soft_relu_pair(a_, eps, d1);
+      gp += k1 * d1;
     }
     w.gdev[0 * TG + e] = gp;
     w.gdev[1 * TG + e] = gq;
@@ -788,7 +804,11 @@ __device__ void bus_balance(const EvalArgs& a, int blk, double* smem) {
     const double dp = p.load_p[ti] + fl[0] - sp_;
     const double dq = p.load_q[ti] + fl[1] - sq;
     const double kb = p.dt[t] * beta;
-    const double lp = kb * p.c_p * soft_abs_d(dp, eps), lq = kb * p.c_q * soft_abs_d(dq, eps);
+    // |.|_eps = sqrt(v^2 + eps^2) and its derivative v / |.|_eps from one
+    // reciprocal square root each (0 where both vanish)
+    const double xp = fma(dp, dp, eps * eps), xq = fma(dq, dq, eps * eps);
+    const double rp = xp > 0.0 ? rsqrt_nr(xp) : 0.0, rq = xq > 0.0 ? rsqrt_nr(xq) : 0.0;
+    const double lp = kb * p.c_p * (dp * rp), lq = kb * p.c_q * (dq * rq);
     w.lamp[ti] = lp;
     w.lamq[ti] = lq;
     // the same multipliers per generator of the bus (read by k_final)
@@ -797,7 +817,7 @@ __device__ void bus_balance(const EvalArgs& a, int blk, double* smem) {
       w.lamg[e] = lp;
       w.lamqg[e] = lq;
     }
-    part[0] = kb * (p.c_p * sqrt(dp * dp + eps * eps) + p.c_q * sqrt(dq * dq + eps * eps));
+    part[0] = kb * (p.c_p * (xp * rp) + p.c_q * (xq * rq));
   }
   block_sum<1>(part, smem);
   if (tid == 0) w.tpart[a.toff.bal + blk] = part[0];
