@@ -721,15 +721,19 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
 constexpr int kSlabLds = 4 * 4 * 256;
 static_assert(kSlabLds >= 2 * kSegChunk + 8 * kBlock, "LDS carve");
 
-// Base-case DC flows of 16 branches for every period, on FP64 MFMA, with the
+// Base-case DC flows of 16 branches for 16 periods, on FP64 MFMA, with the
 // uniform slack folded into the operand: F[t][l] = sum_j p_tj (ISF[l][bus(j)]
 // - rowsum_l / N) - c[t][l], where the per-grid constant c holds the loads'
 // part (ISF load_t - rowsum_l sum_i load_ti / N).  Also the outaged branches'
-// flows.
-__device__ void flow_slab(const EvalArgs& a, int slab, double* smem) {
+// flows.  One block per (16 branches, 16 periods): a single row tile keeps
+// eight k-steps of operands in flight (the k-loop's load round trips, not
+// the MFMAs, set a slab's time).
+__device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int T = p.T, G = p.G, Lp = p.Lp, Kp = p.Kp, N = p.N;
+  const int mtiles = p.Tp / 16;
+  const int slab = blk / mtiles, r0 = (blk - slab * mtiles) * 16;
   const double* xP = a.x + 2 * (size_t)T * N;
   const int n0 = slab * 16;
   double* F = w.F;
@@ -737,21 +741,23 @@ __device__ void flow_slab(const EvalArgs& a, int slab, double* smem) {
   const int* kof = p.kof;
   const double* cload = p.cload;
   auto aload = [=](int k, int row) -> double {
-    return (row < T && k < G) ? xP[(size_t)row * G + k] : 0.0;
+    const int t = r0 + row;
+    return (t < T && k < G) ? xP[(size_t)t * G + k] : 0.0;
   };
   auto epi = [=](int row, int col, double v) {
-    if (row < T) {
-      const double f = v - cload[(size_t)row * Lp + col];
-      F[(size_t)row * Lp + col] = f;
+    const int t = r0 + row;
+    if (t < T) {
+      const double f = v - cload[(size_t)t * Lp + col];
+      F[(size_t)t * Lp + col] = f;
       const int k = kof[col];
-      if (k >= 0) Fk[(size_t)row * Kp + k] = f;
+      if (k >= 0) Fk[(size_t)t * Kp + k] = f;
     }
   };
-  mfma_slab_dispatch<4>(p.Tp / 16, aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
+  mfma_slab<1, 8>(aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
 }
 
 // Blocks [0, nb_br): branch forward; [nb_br, nb_br + T): one period each;
-// then Lp / 16 flow slabs.
+// then (Lp / 16) x (Tp / 16) flow slabs.
 __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
   __shared__ double smem[kSlabLds];
   StepParams sp;
@@ -1780,7 +1786,8 @@ static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, 
 static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStream_t s) {
   switch (stage) {
     case 0:
-      hipLaunchKernelGGL(k_forward, dim3(pr->nb_br + pr->T + pr->Lp / 16), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL(k_forward, dim3(pr->nb_br + pr->T + pr->Lp / 16 * (pr->Tp / 16)),
+                         dim3(kBlock), 0, s, a);
       break;
     case 1:
       if (pr->K > 0) {
