@@ -304,9 +304,8 @@ qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacit
  * wavefront (8, 16 or 32), wl wavefronts per block (1, 2, 4 or 8) stacked
  * along the branches with bl*wl >= 16, and tc periods per block (0: a default
  * from the problem size; at most 8, and at most T).  A new problem starts
- * with bl 8, wl 8 and the default tc and lt below 32 periods, and from 32
- * periods with the period-split tile of qg_set_ctg_tile_split (wl 4, tcw 4,
- * default lt).  The results do not depend on the
+ * with the period-split tile of qg_set_ctg_tile_split (wl 4, tcw 2 below 32
+ * periods and 4 from there, default lt).  The results do not depend on the
  * tile except through the order of floating-point sums.  A step graph cached
  * by qg_solve is re-captured after a change.  Errors: ARG.
  */
@@ -326,8 +325,7 @@ qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
 qg_status qg_set_ctg_ltiles(qg_problem* prob, int32_t lt);
 
 /*
- * Period-split tile of the contingency map-reduce (the default from 32
- * periods): a
+ * Period-split tile of the contingency map-reduce (the default form): a
  * block of wl wavefronts (1..8) covers lt consecutive tiles of 8 branches (lt
  * in [2, 64], or 0 for the default of qg_set_ctg_ltiles) and 64
  * contingencies, and its wavefronts split the periods, tcw (1..8) each, so a

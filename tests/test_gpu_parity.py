@@ -193,7 +193,8 @@ def test_ctg_split_tile_invariance(qg, wl, tcw, lt):
     oversized branch ranges."""
     c = case("c2")
     prob = qg.Problem(c)
-    assert prob.dims["ctg_split"] == 0          # the default below 32 periods
+    assert prob.dims["ctg_split"] == 1          # the default form
+    assert prob.tile() == f"s4x2x{prob.dims['ctg_lt']}"
     x = synth.random_point(c, 10, spread=0.3)
     prob.set_ctg_tile(8, 8, 4, lt=1)
     assert prob.dims["ctg_split"] == 0
@@ -231,7 +232,7 @@ def test_ctg_split_tiles_c3_against_oracle(qg):
     tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
     for tile in (None, (8, 6, 8)):
         prob = qg.Problem(c)
-        assert prob.dims["ctg_split"] == 1      # the default from 32 periods
+        assert prob.tile() == f"s4x4x{prob.dims['ctg_lt']}"   # four periods a wavefront from 32
         if tile:
             prob.set_ctg_tile_split(*tile)
         t, g = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
