@@ -1204,6 +1204,9 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 // chunk the worst penalty (smallest index on ties) and the sum.  One 64-thread
 // block per (chunk, t); all partial loads of a lane are in flight together.
 
+// flagged l-block partials loaded together by the sparse reduction
+constexpr int kZredBatch = 32;
+
 template <bool SPARSE>
 __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   const DevProblem& p = a.p;
@@ -1216,7 +1219,7 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   const size_t o = (size_t)t * Kp + s;
   const size_t stride = (size_t)T * Kp;
   // the l-block partials in l-block order; after the period-split
-  // map-reduce only the flagged ones (the others are all zero), up to 16 of
+  // map-reduce only the flagged ones (the others are all zero), up to 32 of
   // each in flight
   double zs = 0.0, ss = 0.0;
   if constexpr (!SPARSE) {
@@ -1227,20 +1230,20 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
   for (int b0 = 0; SPARSE && b0 < a.nLb; b0 += 64) {
     uint64_t m = __builtin_amdgcn_ballot_w64(b0 + lane < a.nLb && zf[b0 + lane] != 0);
     while (m) {
-      int idx[16];
+      int idx[kZredBatch];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < kZredBatch; ++u) {
         idx[u] = m ? b0 + __builtin_ctzll(m) : -1;
         m &= m - 1;
       }
-      double vz[16], vs[16];
+      double vz[kZredBatch], vs[kZredBatch];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < kZredBatch; ++u) {
         vz[u] = idx[u] >= 0 ? w.zpart[o + (size_t)idx[u] * stride] : 0.0;
         vs[u] = idx[u] >= 0 ? w.spart[o + (size_t)idx[u] * stride] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < kZredBatch; ++u) {
         zs += vz[u];
         ss += vs[u];
       }
