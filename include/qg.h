@@ -317,8 +317,8 @@ qg_status qg_set_ctg_tile(qg_problem* prob, int32_t bl, int32_t wl, int32_t tc);
  * least 2 for a period-split tile), or 0 for the default (doubling from 1,
  * or 2, while at least 2048 blocks remain, at most 8).  More tiles per block
  * spread each block's fixed costs and shrink the per-(period, contingency)
- * partial sums; fewer leave more blocks.  qg_set_ctg_tile and
- * qg_set_ctg_tile_split reset it to the default.
+ * partial sums; fewer leave more blocks.  qg_set_ctg_tile resets it to the
+ * default; qg_set_ctg_tile_split sets it (0: the default).
  * Results depend on it only through the order of floating-point sums.  A
  * step graph cached by qg_solve is re-captured after a change.  Errors: ARG.
  */
