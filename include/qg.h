@@ -167,6 +167,10 @@ typedef struct {
   double stop_ratio;     /* stop once score / z_ed >= stop_ratio (if z_ed > 0) */
   int32_t use_graph;     /* 1: replay captured HIP graphs; 0: plain launches */
   int32_t profile;       /* 1: time each kernel with events (plain launches) */
+  int32_t skip_final;    /* 1: no end-of-call score evaluation and no read of the
+                          * last objective (final_loss, final_score and terms are
+                          * NaN): the call ends with the last step */
+  int32_t reserved;      /* must be 0 */
 } qg_solve_opts;
 
 #define QG_NKERNELS 8
@@ -182,6 +186,10 @@ typedef struct {
    * k_ctg_main, k_ctg_zred, k_ctg_asm, k_adjoint, k_final (slots 6, 7 unused) */
   double kernel_ms[QG_NKERNELS];
   int64_t kernel_calls[QG_NKERNELS];
+  /* device time of the steps, from HIP events on the solve's stream around
+   * them (the schedule upload, every step and any gap checks in between;
+   * not the end-of-call score): milliseconds */
+  double steps_ms;
 } qg_solve_report;
 
 typedef struct qg_problem qg_problem;

@@ -6,8 +6,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <vector>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "qg_internal.h"
 
@@ -50,6 +51,47 @@ void drop_graph(qg::Problem& p) {
     (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p.graph_exec));
     p.graph_exec = nullptr;
   }
+  for (auto& g : p.step_graph) {
+    if (g) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(g));
+    g = nullptr;
+  }
+}
+
+// Pinned staging of the schedule table and the step-timing events, created
+// at a problem's first solve and kept until it is destroyed.
+qg_status solve_resources(qg::Problem& p) {
+  if (!p.sched_host) {
+    void* h = nullptr;
+    hipError_t e = hipHostMalloc(&h, 2 * (size_t)qg::kSchedCap * qg::kSchedStride * sizeof(double),
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "pinned schedule table");
+    p.sched_host = static_cast<double*>(h);
+  }
+  for (auto& ev : p.sched_ev)
+    if (!ev) {
+      hipEvent_t x;
+      hipError_t e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "event");
+      ev = x;
+    }
+  for (auto& ev : p.step_ev)
+    if (!ev) {
+      hipEvent_t x;
+      hipError_t e = hipEventCreate(&x);
+      if (e != hipSuccess) return hip_fail(e, "event");
+      ev = x;
+    }
+  return QG_OK;
+}
+
+void release_solve_resources(qg::Problem& p) {
+  if (p.sched_host) (void)hipHostFree(p.sched_host);
+  p.sched_host = nullptr;
+  for (auto* set : {&p.sched_ev, &p.step_ev})
+    for (auto& ev : *set) {
+      if (ev) (void)hipEventDestroy(static_cast<hipEvent_t>(ev));
+      ev = nullptr;
+    }
 }
 
 // Set sizes of the screening options (Alg. 2): worst slots and slots in all.
@@ -363,7 +405,15 @@ qg_status qg_set_ctg_ltiles(qg_problem* pr, int32_t lt) {
   return QG_OK;
 }
 
+qg_status eval_grad_in(qg_problem* pr, const double* d_x, double* d_grad, double* d_terms,
+                       const qg_homotopy* h, void* d_workspace, void* stream);
+
 qg_status qg_eval_grad(qg_problem* pr, const double* d_x, double* d_grad, double* d_terms,
+                       const qg_homotopy* h, void* d_workspace, void* stream) {
+  return eval_grad_in(pr, d_x, d_grad, d_terms, h, d_workspace, stream);
+}
+
+qg_status eval_grad_in(qg_problem* pr, const double* d_x, double* d_grad, double* d_terms,
                        const qg_homotopy* h, void* d_workspace, void* stream) {
   qg_status s = check_problem(pr);
   if (s != QG_OK) return s;
@@ -499,6 +549,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   if (s != QG_OK) return s;
   if (o->profile && pr->p.scr.on)
     return fail(QG_ERR_ARG, "profile mode times the exact step: turn screening off");
+  if (o->reserved != 0) return fail(QG_ERR_ARG, "reserved field must be 0");
+  s = solve_resources(pr->p);
+  if (s != QG_OK) return s;
   const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
 
   const qg::Problem& p = pr->p;
@@ -528,11 +581,55 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   qg::EvalMode sm_run = sm;
   sm_run.screened = scr ? 1 : 0;
 
-  std::vector<double> table((size_t)qg::kSchedCap * qg::kSchedStride, 0.0);
+  // The device table holds the schedule rows of up to kSchedCap consecutive
+  // iterations.  A chunk of steps whose rows are already there (same
+  // schedule, same workspace: a later call of the same solve) only sets the
+  // step counter; otherwise the rows from its first iteration to the end of
+  // the horizon (at most kSchedCap) are filled in one half of the pinned
+  // staging buffer and copied on the stream.  A half is refilled only after
+  // the event behind its previous copy (the copies are asynchronous).
+  unsigned char skey[sizeof(pr->p.sched_key)];
+  {
+    std::memset(skey, 0, sizeof(skey));
+    size_t at = 0;
+    auto put = [&](const void* v, size_t n) { std::memcpy(skey + at, v, n); at += n; };
+    const void* wsp = d_workspace;
+    put(&wsp, sizeof(wsp));
+    put(&n_total, sizeof(n_total));
+    put(o->alpha0, sizeof(o->alpha0));
+    put(o->alphaf, sizeof(o->alphaf));
+    const double sc[8] = {o->eps0, o->epsf, o->beta0, o->betaf, o->rho0, o->rhof,
+                          cfg->beta1, cfg->beta2};
+    put(sc, sizeof(sc));
+    static_assert(8 + 8 + 2 * 6 * 8 + 8 * 8 <= sizeof(skey), "schedule key size");
+  }
+  int half = 0;
+  bool half_used[2] = {false, false};
   auto upload = [&](int64_t first, int count) -> qg_status {
-    fill_schedule(table.data(), o, cfg, n_total, first, count);
-    HIP_TRY(hipMemcpyAsync(w.sched, table.data(), (size_t)count * qg::kSchedStride * sizeof(double),
+    qg::Problem& pm = pr->p;
+    if (pm.sched_base >= 1 && std::memcmp(skey, pm.sched_key, sizeof(skey)) == 0 &&
+        first >= pm.sched_base && first + count <= pm.sched_base + pm.sched_rows) {
+      const bool continues = first == pm.sched_next;
+      pm.sched_next = -1;  // set again once this chunk's steps are enqueued
+      if (!continues && qg::launch_set_step(&p, w, first - pm.sched_base, ex) != 0)
+        return hip_fail(hipGetLastError(), "launch");
+      return QG_OK;
+    }
+    pm.sched_next = -1;
+    const int rows = (int)std::min<int64_t>(qg::kSchedCap, n_total - first + 1);
+    double* table = pm.sched_host + (size_t)half * qg::kSchedCap * qg::kSchedStride;
+    hipEvent_t done_ev = static_cast<hipEvent_t>(pm.sched_ev[half]);
+    if (half_used[half]) HIP_TRY(hipEventSynchronize(done_ev), "event sync");
+    fill_schedule(table, o, cfg, n_total, first, rows);
+    pm.sched_base = -1;
+    HIP_TRY(hipMemcpyAsync(w.sched, table, (size_t)rows * qg::kSchedStride * sizeof(double),
                            hipMemcpyHostToDevice, ex), "schedule upload");
+    HIP_TRY(hipEventRecord(done_ev, ex), "event record");
+    half_used[half] = true;
+    half ^= 1;
+    std::memcpy(pm.sched_key, skey, sizeof(skey));
+    pm.sched_base = first;
+    pm.sched_rows = rows;
     if (qg::launch_set_step(&p, w, 0, ex) != 0) return hip_fail(hipGetLastError(), "launch");
     return QG_OK;
   };
@@ -565,12 +662,13 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     for (auto& e : evs) HIP_TRY(hipEventCreate(&e), "event");
   }
 
-  // graph of gsteps consecutive steps (the step counter lives on the device);
-  // one graph launch costs about as much as several kernels, so it covers
-  // up to 32 steps
-  int gsteps = (int)std::min<int64_t>(32, o->n_steps);
-  // screening: one graph per refresh cycle (the exact step, the selection and
-  // the R - 1 screened steps), so the refresh adds no launch gaps
+  // plain steps replay the cached graphs of 2^i consecutive steps (the step
+  // counter lives on the device): a call of n steps launches one graph per
+  // set bit of n (at most 32 steps per launch), whatever n is, so calls of
+  // different lengths share the same graphs.  Screening: one graph per
+  // refresh cycle (the exact step, the selection and the R - 1 screened
+  // steps), so the refresh adds no launch gaps
+  int gsteps = 0;
   if (scr) gsteps = (R >= 2 && R <= kCycleMax && o->n_steps >= R) ? (int)R : 0;
   if (scr && pr->p.scr.n_act != pr->p.scr.cap) {
     // a smaller set given by the caller: the solve works with full-size sets,
@@ -580,12 +678,13 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     pr->p.scr.Ka = (int)qg::round_up(pr->p.scr.cap, qg::kCtgLanes);
     drop_graph(pr->p);
   }
-  hipGraphExec_t gexec = nullptr;  // used only when it holds this call's steps
-  if (graph && gsteps >= 4) {
-    gexec = static_cast<hipGraphExec_t>(pr->p.graph_exec);
+  hipGraphExec_t gexec = nullptr;  // screening: the cycle graph, when it holds this call's steps
+  bool step_graphs = false;        // plain steps: the cached 2^i-step graphs are current
+  if (graph && (scr ? gsteps >= 4 : o->n_steps > 0)) {
     const void* key[5] = {d_x, d_m, d_v, d_workspace, nullptr};
-    bool hit = gexec && std::memcmp(key, pr->p.graph_key, sizeof(key)) == 0 &&
-               pr->p.graph_steps == gsteps;
+    bool hit = (scr ? pr->p.graph_exec != nullptr : pr->p.step_graph[0] != nullptr) &&
+               std::memcmp(key, pr->p.graph_key, sizeof(key)) == 0 &&
+               (!scr || pr->p.graph_steps == gsteps);
     // the schedule constants are kernel arguments, so a different schedule
     // needs a new capture as well
     if (hit && std::memcmp(&pr->p.graph_mode, &sm_run, sizeof(sm_run)) != 0) hit = false;
@@ -595,28 +694,44 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
                 gt.lt != p.tile.lt || gt.split != p.tile.split))
       hit = false;
     if (!hit) {
-      if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; pr->p.graph_exec = nullptr; }
-      hipGraph_t g;
-      HIP_TRY(hipStreamBeginCapture(pr->own, hipStreamCaptureModeThreadLocal), "begin capture");
+      drop_graph(pr->p);
+      auto capture = [&](int nsteps, bool cycle, void** slot) -> qg_status {
+        hipGraph_t g;
+        hipGraphExec_t ge = nullptr;
+        HIP_TRY(hipStreamBeginCapture(pr->own, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (cycle) {
+          qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, pr->own, nullptr);
+          qg::launch_screen_select(&p, w, -1, pr->own);
+          for (int k = 1; k < nsteps; ++k)
+            qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+        } else {
+          for (int k = 0; k < nsteps; ++k)
+            qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+        }
+        HIP_TRY(hipStreamEndCapture(pr->own, &g), "end capture");
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        *slot = ge;
+        return QG_OK;
+      };
       if (scr) {
-        qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm, 1, d_m, d_v, pr->own, nullptr);
-        qg::launch_screen_select(&p, w, -1, pr->own);
-        for (int k = 1; k < gsteps; ++k)
-          qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+        s = capture(gsteps, true, &pr->p.graph_exec);
       } else {
-        for (int k = 0; k < gsteps; ++k)
-          qg::launch_eval(&p, w, d_x, nullptr, nullptr, sm_run, 1, d_m, d_v, pr->own, nullptr);
+        for (int i = 0; i < qg::kStepGraphs && s == QG_OK; ++i)
+          s = capture(1 << i, false, &pr->p.step_graph[i]);
       }
-      HIP_TRY(hipStreamEndCapture(pr->own, &g), "end capture");
-      hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-      pr->p.graph_exec = gexec;
+      if (s != QG_OK) {
+        drop_graph(pr->p);
+        return s;
+      }
       std::memcpy(pr->p.graph_key, key, sizeof(key));
-      pr->p.graph_steps = gsteps;
+      pr->p.graph_steps = scr ? gsteps : 0;
       std::memcpy(&pr->p.graph_mode, &sm_run, sizeof(sm_run));
       pr->p.graph_tile = p.tile;
     }
+    if (scr) gexec = static_cast<hipGraphExec_t>(pr->p.graph_exec);
+    else step_graphs = true;
   }
 
   // screening: steps [done0, done0 + n) of this call, the step of iteration
@@ -653,10 +768,14 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
 
   auto run_steps = [&](int64_t n) -> qg_status {
     int64_t left = n;
-    if (graph && gexec) {
-      while (left >= gsteps) {
-        HIP_TRY(hipGraphLaunch(gexec, ex), "graph launch");
-        left -= gsteps;
+    if (step_graphs) {
+      for (int i = qg::kStepGraphs - 1; i >= 0; --i) {
+        const int64_t len = int64_t(1) << i;
+        while (left >= len) {
+          HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(pr->p.step_graph[i]), ex),
+                  "graph launch");
+          left -= len;
+        }
       }
     }
     if (profile) {
@@ -697,6 +816,9 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     return QG_OK;
   };
 
+  hipEvent_t ev_steps0 = static_cast<hipEvent_t>(pr->p.step_ev[0]);
+  hipEvent_t ev_steps1 = static_cast<hipEvent_t>(pr->p.step_ev[1]);
+  HIP_TRY(hipEventRecord(ev_steps0, ex), "event record");
   int64_t done = 0;
   while (done < o->n_steps) {
     int64_t n = o->n_steps - done;
@@ -707,6 +829,8 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
     s = scr ? run_screened(done, n) : run_steps(n);
     if (s != QG_OK) return s;
     done += n;
+    // every scheduled step advanced the device counter by one
+    pr->p.sched_next = o->iter0 + done + 1;
     if (o->check_every > 0 && (done % o->check_every == 0) && o->z_ed > 0.0) {
       double tot, terms[QG_NTERMS];
       s = eval_score(&tot, terms);
@@ -719,9 +843,24 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
       }
     }
   }
+  HIP_TRY(hipEventRecord(ev_steps1, ex), "event record");
   HIP_TRY(hipStreamSynchronize(ex), "sync");
   rep->steps_done = done;
   rep->wall_s = std::chrono::duration<double>(clock::now() - t_start).count();
+  {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev_steps0, ev_steps1), "elapsed");
+    rep->steps_ms = ms;
+  }
+  if (profile) {
+    for (int q = 0; q < kKernels; ++q)
+      if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
+  }
+  if (o->skip_final) {
+    rep->final_loss = rep->final_score = std::nan("");
+    for (double& t : rep->terms) t = std::nan("");
+    return QG_OK;
+  }
   // objective at the last schedule point was left in the workspace terms
   double last[QG_NTERMS];
   // on the solve's own stream: a legacy-stream copy would conflict with a
@@ -733,10 +872,6 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   s = eval_score(&tot, rep->terms);
   if (s != QG_OK) return s;
   rep->final_score = -tot;
-  if (profile) {
-    for (int q = 0; q < kKernels; ++q)
-      if (rep->kernel_calls[q]) rep->kernel_ms[q] /= (double)rep->kernel_calls[q];
-  }
   return QG_OK;
 }
 
@@ -810,6 +945,10 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
 
   const auto t_start = clock::now();
   std::vector<double> table((size_t)qg::kSchedCap * qg::kSchedStride, 0.0);
+  for (int i = 0; i < n; ++i) {  // their tables and counters are rewritten here
+    probs[i]->p.sched_base = -1;
+    probs[i]->p.sched_next = -1;
+  }
   int64_t done = 0;
   while (done < o->n_steps) {
     const int64_t nc = std::min<int64_t>(o->n_steps - done, qg::kSchedCap);
@@ -899,7 +1038,8 @@ qg_status qg_debug_fetch(const qg_problem* pr, const void* d_workspace, const ch
 
 void qg_destroy_problem(qg_problem* pr) {
   if (!pr) return;
-  if (pr->p.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(pr->p.graph_exec));
+  drop_graph(pr->p);
+  release_solve_resources(pr->p);
   if (pr->own) (void)hipStreamDestroy(pr->own);
   pr->alive = false;
   delete pr;

@@ -20,6 +20,7 @@ constexpr int kCtgLdsBytes = 64 * 1024; // LDS budget of one contingency block
 constexpr int kAdjStepsPerBlock = 32;   // MFMA k-steps per block of the adjoint product
 constexpr int kSchedCap = 2048;         // solve steps per uploaded schedule table
 constexpr int kSchedStride = 16;        // doubles per step in the schedule table
+constexpr int kStepGraphs = 6;          // cached step graphs of 1, 2, 4, ..., 32 steps
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -195,8 +196,11 @@ struct Problem {
   size_t const_bytes, work_bytes;
   DevProblem dp;
   void* arena = nullptr;
-  // graph cache of qg_solve
+  // graph cache of qg_solve: graph_exec holds one screening refresh cycle;
+  // step_graph[i] holds 2^i plain steps (i < kStepGraphs), so that a solve of
+  // any length replays cached graphs (n = sum of powers of two)
   void* graph_exec = nullptr;
+  void* step_graph[kStepGraphs] = {};
   const void* graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int graph_steps = 0;
   EvalMode graph_mode{};
@@ -208,6 +212,23 @@ struct Problem {
   std::vector<double> dt_host;   // [T]
   double load_value = 0.0;
   Screen scr;
+  // pinned host staging of the schedule table (two halves, each reused only
+  // after the event recorded behind its last upload), and the events that
+  // time a solve's steps; created at the first qg_solve
+  double* sched_host = nullptr;
+  void* sched_ev[2] = {nullptr, nullptr};
+  // what the device schedule table holds: rows of iterations
+  // [sched_base, sched_base + sched_rows) for the schedule sched_key (bytes
+  // of the solve options and Adam constants the rows depend on, and the
+  // workspace they live in); sched_base < 1 when unknown
+  unsigned char sched_key[192] = {};
+  int64_t sched_base = -1;
+  int sched_rows = 0;
+  // iteration the device step counter and the copied-ahead row point at
+  // after the last scheduled step (-1: unknown); a call continuing there
+  // needs no counter reset
+  int64_t sched_next = -1;
+  void* step_ev[2] = {nullptr, nullptr};
 };
 
 // Host build products (before upload).

@@ -97,7 +97,8 @@ class qg_solve_opts(C.Structure):
                 ("eps0", C.c_double), ("epsf", C.c_double), ("beta0", C.c_double),
                 ("betaf", C.c_double), ("rho0", C.c_double), ("rhof", C.c_double),
                 ("z_ed", C.c_double), ("stop_ratio", C.c_double),
-                ("use_graph", C.c_int32), ("profile", C.c_int32)]
+                ("use_graph", C.c_int32), ("profile", C.c_int32),
+                ("skip_final", C.c_int32), ("reserved", C.c_int32)]
 
 
 class qg_solve_report(C.Structure):
@@ -106,7 +107,8 @@ class qg_solve_report(C.Structure):
                 ("final_loss", C.c_double), ("final_score", C.c_double),
                 ("terms", C.c_double * QG_NTERMS),
                 ("kernel_ms", C.c_double * QG_NKERNELS),
-                ("kernel_calls", C.c_int64 * QG_NKERNELS)]
+                ("kernel_calls", C.c_int64 * QG_NKERNELS),
+                ("steps_ms", C.c_double)]
 
 
 class qg_screen_opts(C.Structure):
@@ -285,6 +287,7 @@ def qg_eval_grad(h, d_x, d_grad, d_terms, hom, d_ws, stream):
            "qg_eval_grad")
 
 
+
 def qg_time_stage(h, d_x, hom, stage, reps, d_ws, stream):
     out = C.c_double(0.0)
     _check(lib.qg_time_stage(h, d_x, C.byref(hom), int(stage), int(reps), d_ws, stream,
@@ -319,7 +322,7 @@ def qg_destroy_problem(h):
 
 def solve_opts(n_steps, alpha0, alphaf=None, iter0=0, n_total=0, check_every=0, eps0=1e-2,
                epsf=1e-2, beta0=1.0, betaf=1.0, rho0=1.0, rhof=1.0, z_ed=0.0,
-               stop_ratio=0.99, use_graph=1, profile=0):
+               stop_ratio=0.99, use_graph=1, profile=0, skip_final=0):
     alpha0 = list(alpha0) if np.ndim(alpha0) else [float(alpha0)] * QG_NCLASS
     alphaf = alpha0 if alphaf is None else (
         list(alphaf) if np.ndim(alphaf) else [float(alphaf)] * QG_NCLASS)
@@ -327,7 +330,8 @@ def solve_opts(n_steps, alpha0, alphaf=None, iter0=0, n_total=0, check_every=0, 
         n_steps=n_steps, iter0=iter0, n_total=n_total, check_every=check_every,
         alpha0=(C.c_double * QG_NCLASS)(*alpha0), alphaf=(C.c_double * QG_NCLASS)(*alphaf),
         eps0=eps0, epsf=epsf, beta0=beta0, betaf=betaf, rho0=rho0, rhof=rhof, z_ed=z_ed,
-        stop_ratio=stop_ratio, use_graph=use_graph, profile=profile)
+        stop_ratio=stop_ratio, use_graph=use_graph, profile=profile,
+        skip_final=1 if skip_final else 0, reserved=0)
 
 
 def adam_cfg(beta1=0.9, beta2=0.999, eps=1e-8, eps_in_numerator=False):
@@ -509,7 +513,8 @@ def report_dict(rep):
                 final_score=rep.final_score,
                 terms=dict(zip(TERM_NAMES, list(rep.terms))),
                 kernel_ms=dict(zip(KERNEL_NAMES, list(rep.kernel_ms)[:len(KERNEL_NAMES)])),
-                kernel_calls=dict(zip(KERNEL_NAMES, list(rep.kernel_calls)[:len(KERNEL_NAMES)])))
+                kernel_calls=dict(zip(KERNEL_NAMES, list(rep.kernel_calls)[:len(KERNEL_NAMES)])),
+                steps_ms=rep.steps_ms)
 
 
 class MLP:

@@ -425,6 +425,39 @@ def test_graph_recaptured_after_tile_change(qg):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_split_solve_equals_one_call(qg):
+    """A solve split over several calls of one schedule (graphs of 2^i steps,
+    the resident schedule table, the step counter left where the previous
+    call ended) gives bit for bit the points of one call of all the steps,
+    also with a call of another schedule in between and with eager steps."""
+    import torch
+    c = case("c1")
+    prob = qg.Problem(c)
+    x0 = synth.flat_start(c)
+    opts = dict(n_total=120, alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3, beta0=0.3, rho0=0.5)
+    ref = prob.new_vector(x0)
+    mr, vr = prob.new_vector(), prob.new_vector()
+    prob.solve(ref, mr, vr, qg.solve_opts(57, [1e-3] * 6, use_graph=1, **opts))
+    torch.cuda.synchronize()
+    want = ref.cpu().numpy().copy()
+    xd, md, vd = prob.new_vector(x0), prob.new_vector(), prob.new_vector()
+    other = prob.new_vector(x0)
+    mo, vo = prob.new_vector(), prob.new_vector()
+    it = 0
+    for n, graph in ((7, 1), (13, 1), (3, 0), (1, 1), (20, 1), (13, 1)):
+        prob.solve(xd, md, vd, qg.solve_opts(n, [1e-3] * 6, iter0=it, use_graph=graph,
+                                             skip_final=1, **opts))
+        it += n
+        if it == 20:
+            # another schedule and other buffers between two calls
+            prob.solve(other, mo, vo, qg.solve_opts(5, [2e-3] * 6, n_total=9, use_graph=1))
+    torch.cuda.synchronize()
+    assert it == 57
+    assert np.array_equal(xd.cpu().numpy(), want)
+    rep = prob.solve(xd, md, vd, qg.solve_opts(3, [1e-3] * 6, iter0=it, skip_final=1, **opts))
+    assert np.isnan(rep.final_score) and rep.steps_done == 3 and rep.steps_ms > 0.0
+
+
 def test_no_contingency_grid(qg):
     """A radial grid has no non-islanding outage: K = 0, C_ctg = 0."""
     c = tiny_case(5, [0, 1, 2, 1], [1, 2, 3, 4], [0.1, 0.2, 0.1, 0.15], [0, 3], T=3,
