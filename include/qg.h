@@ -252,6 +252,28 @@ qg_status qg_eval_grad(qg_problem* prob, const double* d_x, double* d_grad,
                        void* stream);
 
 /*
+ * qg_eval_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels, same results as
+ * qg_eval_grad; its scratch is a static device array of QG_NOALLOC_SCRATCH
+ * bytes inside the library, one per GPU, resolved at the first call on each
+ * device and held until the process ends.  The caller still passes x and the
+ * outputs (d_grad, d_terms: device, as for qg_eval_grad).
+ *   Allocates nothing: no hipMalloc, hipFree or allocating library call.
+ *   The current device must be the one the problem was built on (ARG
+ *   otherwise).  A problem whose workspace_bytes exceeds QG_NOALLOC_SCRATCH
+ *   is rejected with ARG.
+ *   Every call on one GPU shares that GPU's array and leaves its contents
+ *   behind (nothing in it needs to start at zero).  Calls that overlap on
+ *   one GPU (two streams, two threads, a capture replayed beside another
+ *   call) race on it: order them.
+ * Errors: ARG, STATE, NONFINITE (QG_FLAG_CHECK_FINITE), DEVICE.
+ */
+#define QG_NOALLOC_SCRATCH ((size_t)32 << 20)
+qg_status qg_eval_grad_noalloc(qg_problem* prob, const double* d_x, double* d_grad,
+                               double* d_terms, const qg_homotopy* h, void* stream);
+
+/*
  * One modified-Adam step with clip (Alg. 3) on device arrays of length n_x:
  * m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
  * x <- clip(x - lr_c (m/(1-b1^iter) [+eps]) / (sqrt(v/(1-b2^iter)) + eps)),

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -114,6 +115,30 @@ qg_status screen_counts(const qg::Problem& p, const qg_screen_opts* o, int* n_to
 // Evaluations score the chosen set once screening is on and a set exists.
 bool screened(const qg::Problem& p) { return p.scr.on && p.scr.chosen; }
 
+// Scratch of qg_eval_grad_noalloc: a static device array, one copy per GPU.
+// In host code its name is a host-side stand-in, never a device address:
+// the device address is looked up once per device with hipGetSymbolAddress
+// (that device current) and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[QG_NOALLOC_SCRATCH];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+qg_status noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(QG_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+    if (!ptr || !aligned(ptr)) return fail(QG_ERR_DEVICE, "static scratch is not 256-byte aligned");
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return QG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -169,6 +194,8 @@ qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pr->own, hipStreamNonBlocking);
   if (e != hipSuccess) { delete pr; return hip_fail(e, "upload of the constant arena"); }
   qg::rebase_pointers(&pr->p, d_const_arena);
+  e = hipGetDevice(&pr->p.device);
+  if (e != hipSuccess) { qg_destroy_problem(pr); return hip_fail(e, "current device"); }
   *out = pr;
   return QG_OK;
 }
@@ -411,6 +438,25 @@ qg_status eval_grad_in(qg_problem* pr, const double* d_x, double* d_grad, double
 qg_status qg_eval_grad(qg_problem* pr, const double* d_x, double* d_grad, double* d_terms,
                        const qg_homotopy* h, void* d_workspace, void* stream) {
   return eval_grad_in(pr, d_x, d_grad, d_terms, h, d_workspace, stream);
+}
+
+qg_status qg_eval_grad_noalloc(qg_problem* pr, const double* d_x, double* d_grad,
+                               double* d_terms, const qg_homotopy* h, void* stream) {
+  qg_status s = check_problem(pr);
+  if (s != QG_OK) return s;
+  if (pr->p.work_bytes > QG_NOALLOC_SCRATCH)
+    return fail(QG_ERR_ARG, "workspace of this problem (" + std::to_string(pr->p.work_bytes) +
+                                " bytes) exceeds the static scratch of qg_eval_grad_noalloc (" +
+                                std::to_string((size_t)QG_NOALLOC_SCRATCH) + " bytes)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "current device");
+  if (dev != pr->p.device)
+    return fail(QG_ERR_ARG, "current device " + std::to_string(dev) +
+                                " is not the problem's device " + std::to_string(pr->p.device));
+  void* ws = nullptr;
+  s = noalloc_scratch(dev, &ws);
+  if (s != QG_OK) return s;
+  return eval_grad_in(pr, d_x, d_grad, d_terms, h, ws, stream);
 }
 
 qg_status eval_grad_in(qg_problem* pr, const double* d_x, double* d_grad, double* d_terms,

@@ -176,6 +176,7 @@ size_t screen_bytes(const Problem& p, int cap);
 void carve_screen(const Problem& p, void* buf, int cap, Screen* sc);
 
 struct Problem {
+  int device = -1;  // HIP device current at build (the arena's device)
   // sizes
   int N, L, G, T, M, K;
   int Lp, Kp, G16, G4, Tp;

@@ -42,6 +42,8 @@ QG_FLAG_CHECK_FINITE = 0x1
 QG_FLAG_CTG_FP32 = 0x2
 QG_FLAG_CTG_BF16 = 0x4
 QG_FLAG_CTG_SUM = 0x8
+QG_NOALLOC_SCRATCH = 32 << 20   # bytes of qg_eval_grad_noalloc's static scratch
+
 KERNEL_NAMES = ("k_forward", "k_ctg_main", "k_ctg_zred", "k_ctg_asm", "k_adjoint", "k_final")
 
 _pd = C.POINTER(C.c_double)
@@ -145,6 +147,7 @@ _sig = {
     "qg_set_ctg_ltiles": (C.c_int, [_vp, C.c_int32]),
     "qg_set_ctg_tile_split": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "qg_eval_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp, _vp]),
+    "qg_eval_grad_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_homotopy), _vp]),
     "qg_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double * QG_NCLASS,
                                C.POINTER(qg_adam_cfg), _vp]),
     "qg_solve": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_solve_opts),
@@ -286,6 +289,10 @@ def qg_eval_grad(h, d_x, d_grad, d_terms, hom, d_ws, stream):
     _check(lib.qg_eval_grad(h, d_x, d_grad, d_terms, C.byref(hom), d_ws, stream),
            "qg_eval_grad")
 
+
+def qg_eval_grad_noalloc(h, d_x, d_grad, d_terms, hom, stream):
+    _check(lib.qg_eval_grad_noalloc(h, d_x, d_grad, d_terms, C.byref(hom), stream),
+           "qg_eval_grad_noalloc")
 
 
 def qg_time_stage(h, d_x, hom, stage, reps, d_ws, stream):
@@ -439,6 +446,16 @@ class Problem:
                      terms.data_ptr(), qg_homotopy(eps, beta, rho_scale),
                      self.workspace.data_ptr(), self._stream())
         return terms[:QG_NTERMS], g
+
+    def eval_grad_noalloc(self, x, eps, beta=1.0, rho_scale=1.0, grad=None, terms=None):
+        """qg_eval_grad_noalloc into caller-given outputs (device tensors:
+        grad [n_x] FP64 or None, terms of at least QG_NTERMS FP64 or None);
+        the library's static scratch replaces the workspace."""
+        qg_eval_grad_noalloc(self.handle, x.data_ptr(),
+                             grad.data_ptr() if grad is not None else None,
+                             terms.data_ptr() if terms is not None else None,
+                             qg_homotopy(eps, beta, rho_scale), self._stream())
+        return terms, grad
 
     def adam_step(self, x, m, v, g, it, lr, cfg=None):
         cfg = cfg or adam_cfg()
