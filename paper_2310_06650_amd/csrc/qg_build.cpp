@@ -177,7 +177,8 @@ WorkLayout work_layout(const Problem& p) {
       T * p.Lp * D,                                     // thr
       T * (size_t)p.nKb_max * p.nLb_max,                // zflag
       T * (size_t)(p.Lp / 8) * rflag_stride(p.nKb_max),   // rflag
-      kSchedStride * D};                                // snext
+      kSchedStride * D,                                 // snext
+      ((size_t)(p.Lp / 8 + 1) * T + 8) * 16 * D};       // fh
   WorkLayout w;
   const int n = (int)(sizeof(cnt) / sizeof(cnt[0]));
   size_t o = 0;
@@ -737,6 +738,7 @@ DevWork carve_workspace(const Problem* p, void* ws) {
   w.zflag = base + wl.off[35];
   w.rflag = base + wl.off[36];
   w.snext = D(37);
+  w.fh = D(38);
   return w;
 }
 

@@ -570,7 +570,9 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
     // under FP64 rounding; -1 (every flow passes) where qmax2 alone comes
     // within the margin of the rating
     const double A = p.ctg_smax2[l] * (1.0 - 0x1p-40) - qm2;
-    w.thr[(size_t)t * p.Lp + l] = A > 0.0 ? sqrt(A) * (1.0 - 0x1p-50) : -1.0;
+    const double thr = A > 0.0 ? sqrt(A) * (1.0 - 0x1p-50) : -1.0;
+    w.thr[(size_t)t * p.Lp + l] = thr;
+    w.fh[((size_t)(l >> 3) * T + t) * 16 + 8 + (l & 7)] = thr;
     const size_t TL = (size_t)T * L, e = (size_t)t * L + l;
     w.bco[0 * TL + e] = cs;
     w.bco[1 * TL + e] = sn;
@@ -712,6 +714,7 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
   for (int l = p.L + tid; l < p.Lp; l += kBlock) {
     w.q2[(size_t)t * p.Lp + l] = 0.0;
     w.thr[(size_t)t * p.Lp + l] = -1.0;
+    w.fh[((size_t)(l >> 3) * p.T + t) * 16 + 8 + (l & 7)] = -1.0;
   }
   for (int k = p.K + tid; k < p.Kp; k += kBlock) w.Fk[(size_t)t * p.Kp + k] = 0.0;
 }
@@ -738,6 +741,7 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
   const int n0 = slab * 16;
   double* F = w.F;
   double* Fk = w.Fk;
+  double* FH = w.fh;
   const int* kof = p.kof;
   const double* cload = p.cload;
   auto aload = [=](int k, int row) -> double {
@@ -749,6 +753,7 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
     if (t < T) {
       const double f = v - cload[(size_t)t * Lp + col];
       F[(size_t)t * Lp + col] = f;
+      FH[((size_t)(col >> 3) * T + t) * 16 + (col & 7)] = f;
       const int k = kof[col];
       if (k >= 0) Fk[(size_t)t * Kp + k] = f;
     }
@@ -1061,26 +1066,30 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
   const cdouble* Sc = as_const(p.ctg_smax2);
   const cdouble* Mc = as_const(p.ctg_smax);
   const cdouble* Dc = as_const(p.dt);
-  const cdouble* Fc = as_const(w.F);
   const cdouble* Qc = as_const(w.q2);
-  const cdouble* Hc = as_const(w.thr);
+  const cdouble* FH = as_const(w.fh);
   const double beta = w.params[PB_BETA];
   const R eps = (R)w.params[PB_EPS];
   const R eps2 = eps * eps;
   const int ei = lane >> 3, eg = lane & 7;
   const int l0 = lb * a.lt * 8;
   const int l1 = min(Lp, l0 + a.lt * 8);
-  // FP64: F and thr of the next (period, tile) to be tested
+  // FP64: F and thr of the next (period, tile) to be tested, from the
+  // branch-tiled copy (one 128-byte row per tile and period, so that the
+  // period-ahead prefetch is a fixed offset from the tile's row of period tw)
   double Fn[8], Hn[8];
   if constexpr (kF64) {
-    const size_t e = (size_t)tw * Lp + min(l0, Lp - 8);
+    const cdouble* r = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
-      Fn[g] = Fc[e + g];
-      Hn[g] = Hc[e + g];
+      Fn[g] = r[g];
+      Hn[g] = r[8 + g];
     }
   }
+  const uint32_t live = (1u << ntw) - 1u;  // the wave's periods among the TCW tested
   for (int lbase = l0; lbase < l1; lbase += 8) {
+    const cdouble* cur = FH + ((size_t)(lbase >> 3) * T + tw) * 16;
+    const cdouble* nxt = cur + (size_t)T * 16;  // period tw of the next tile
     R lod[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
@@ -1094,56 +1103,75 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
       for (int j = 0; j < 8; ++j) smx2[j] = (R)Sc[lbase + j];
     }
-    // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
-    R racc = R(0), qacc = R(0);
+    // The test of every (period, branch, lane) of the tile, without a
+    // branch: all TCW periods are tested (the rows past the wave's last
+    // period are spare rows of the array, and their verdicts are dropped
+    // with the mask), and each period's verdict is one bit of hotm.
+    uint32_t hotm = 0;
 #pragma unroll
     for (int i = 0; i < TCW; ++i) {
-      if (i < ntw) {
-        // lanes flagged by any of the eight tests (a ballot per test keeps
-        // the combination in SGPRs)
-        uint64_t hot = 0;
-        R Fr[8];
-        if constexpr (kF64) {
-          double Hr[8];
+      uint64_t hot = 0;
+      if constexpr (kF64) {
+        double Fr[8], Hr[8];
 #pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            Fr[g] = Fn[g];
-            Hr[g] = Hn[g];
-          }
-          // prefetch: the next period of this tile, else period tw of the
-          // next tile (clamped to valid rows at the end)
-          const bool last = i + 1 >= ntw;
-          const int tn = last ? tw : tw + i + 1;
-          const int ln = last ? min(lbase + 8, Lp - 8) : lbase;
-          const size_t e = (size_t)tn * Lp + ln;
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            Fn[g] = Fc[e + g];
-            Hn[g] = Hc[e + g];
-          }
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            const double P = fma_uniform_c(lod[g], fk[i], Fr[g]);
-            hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
-          }
-        } else {
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            Fr[g] = readlane_any(fv, i * 8 + g);
-            const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
-            const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
-            hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
-          }
+        for (int g = 0; g < 8; ++g) {
+          Fr[g] = Fn[g];
+          Hr[g] = Hn[g];
         }
-        if (hot) {
+        // prefetch: the next period of this tile, else period tw of the
+        // next tile (rows past the tile or the last tile are spare rows)
+        const cdouble* q = (i + 1 < TCW) ? cur + 16 * (i + 1) : nxt;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          Fn[g] = q[g];
+          Hn[g] = q[8 + g];
+        }
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const double P = fma_uniform_c(lod[g], fk[i], Fr[g]);
+          hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const R Fr = readlane_any(fv, i * 8 + g);
+          const R P = fma_uniform_c(lod[g], fk[i], Fr);
+          const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
+          hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+        }
+      }
+      hotm |= (hot != 0 ? 1u : 0u) << i;
+    }
+    hotm &= live;
+    // a wave with fewer than TCW periods prefetched a spare row for the
+    // next tile: load its first period's row again
+    if constexpr (kF64) {
+      if (ntw < TCW) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          Fn[g] = nxt[g];
+          Hn[g] = nxt[8 + g];
+        }
+      }
+    }
+    // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
+    R racc = R(0), qacc = R(0);
+    if (hotm) {
+      // the overloaded periods of the tile: the per-branch path, with F,
+      // qmax2 and the ratings loaded again
+#pragma unroll
+      for (int i = 0; i < TCW; ++i) {
+        if ((hotm >> i) & 1u) {
           const R kt = (R)(Dc[tw + i] * p.c_s * beta);
-          R Qr[8], Sr[8];
+          R Fr[8], Qr[8], Sr[8];
 #pragma unroll
           for (int g = 0; g < 8; ++g) {
             if constexpr (kF64) {
+              Fr[g] = cur[16 * i + g];
               Qr[g] = Qc[(size_t)(tw + i) * Lp + lbase + g];
               Sr[g] = Sc[lbase + g];
             } else {
+              Fr[g] = readlane_any(fv, i * 8 + g);
               Qr[g] = readlane_any(qv, i * 8 + g);
               Sr[g] = smx2[g];
             }
@@ -1152,7 +1180,7 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
           for (int g = 0; g < 8; ++g) {
             // the flow formed again (the same fused operation, so the same
-            // value): nothing of the test stays live across the branch
+            // value as in the test)
             const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
             const R s2 = fma(P, P, Qr[g]);
             if (__builtin_amdgcn_ballot_w64(s2 > Sr[g])) {
@@ -1172,11 +1200,11 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
       }
     }
     // per (period, 8 branches): stored only when not all zero, and flagged
-    const uint64_t b = __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0));
+    const uint64_t b = hotm ? __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0)) : 0;
     if (lane < ntw)
       w.rflag[((size_t)(tw + lane) * (Lp / 8) + lbase / 8) * a.rfs + kb] =
           (uint8_t)(((b >> (8 * lane)) & 0xFF) != 0);
-    if (lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
+    if (b != 0 && lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
       const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
       w.rpart[o] = (double)racc;
       w.qpart[o] = (double)qacc;
