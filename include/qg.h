@@ -301,20 +301,35 @@ qg_status qg_solve(qg_problem* prob, double* d_x, double* d_m, double* d_v,
 
 /*
  * Batched solve of independent scenarios (problems built separately, of any
- * sizes): the same schedule and Adam constants for all, n_steps steps each,
- * in one HIP graph per 16 steps in which every scenario's steps form their
- * own branch, so that small scenarios run side by side on the GPU.  Arrays of
- * n entries (n <= QG_BATCH_MAX): problems, x, m, v, workspaces (caller-owned,
- * as for qg_solve) and reports.  No gap checks or profiling (check_every and
- * profile must be 0).  reports[i].wall_s is the batch's wall time of the
- * steps (graph capture excluded).  Synchronises the stream.
+ * sizes; the scenario batching of the many-problem workload): the same
+ * schedule and Adam constants for all, n_steps steps each.  A step is six
+ * launches for the whole batch, one per stage of the single-problem step
+ * (Section II-C to II-G; Alg. 3), each covering every scenario's blocks;
+ * the contingency map-reduce (eqs. (rank_correct), (sfr_pen)-(zctg)) is one
+ * persistent launch whose blocks take (scenario, branch block, contingency
+ * block, period chunk) work items from a counter until none is left.  Steps
+ * are replayed from one HIP graph per 16 steps.  Every scenario gets the
+ * points of its own qg_solve steps, bit for bit.
+ *   Arrays of n entries (n <= QG_BATCH_MAX): problems, x, m, v, workspaces
+ *   (caller-owned, as for qg_solve) and reports.
+ *   d_batch: caller-owned device buffer of at least qg_batch_bytes bytes,
+ *   256-byte aligned (every scenario's kernel arguments, the block tables of
+ *   the six launches and the work counter); overwritten by the call.
+ *   Every problem with contingencies needs a period-split tile of 4
+ *   wavefronts of 4 periods (qg_set_ctg_tile_split(prob, 4, 4, lt); the
+ *   branch tiles per block lt chosen per problem), screening off, and the
+ *   same storage of the outage factors as the others.
+ *   No gap checks or profiling (check_every and profile must be 0).
+ *   reports[i].wall_s and steps_ms time the steps of the whole batch (upload
+ *   of the tables and graph capture excluded).  Synchronises the stream.
  * Errors: ARG, DEVICE.
  */
 #define QG_BATCH_MAX 256
+qg_status qg_batch_bytes(qg_problem* const* probs, int32_t n, size_t* bytes);
 qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x,
                          double* const* d_m, double* const* d_v, void* const* d_workspace,
-                         const qg_solve_opts* opts, const qg_adam_cfg* cfg,
-                         qg_solve_report* reports, void* stream);
+                         void* d_batch, size_t batch_bytes, const qg_solve_opts* opts,
+                         const qg_adam_cfg* cfg, qg_solve_report* reports, void* stream);
 
 /*
  * Padded sizes and launch geometry, for tests and tools: dims[0..15] =

@@ -6,9 +6,10 @@ Builds the scenarios of synth.batch_cases (bus counts 100..2000, 12..48
 periods, every non-islanding outage), picks each one's contingency tile with
 the autotuner, and measures the same number of Adam steps two ways: each
 scenario solved alone in turn (its own step graphs), and all of them in one
-batched solve (qg_solve_batch: one graph per 16 steps with a branch per
-scenario).  Prints one JSON line with scenario-steps per second, contingency
-elements per second and the effective rate of outage-factor bytes.
+batched solve (qg_solve_batch: six launches per step for the whole batch,
+the contingency map-reduce persistent over a work list, 16 steps per graph).
+Prints one JSON line with scenario-steps per second, contingency elements per
+second and the effective rate of outage-factor bytes.
 """
 from __future__ import annotations
 
@@ -27,6 +28,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=4000)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tile", default="s4x4",
+                    help="tile of every scenario with --no-tune (4 wavefronts of 4 periods)")
     args = ap.parse_args()
     import torch
     cases = synth.batch_cases(args.n, seed0=args.seed)
@@ -36,11 +39,13 @@ def main():
     x0s = [synth.flat_start(c) for c in cases]
     tiles = []
     t0 = time.perf_counter()
-    for p, x0 in zip(probs, x0s):
+    for p, x0, c in zip(probs, x0s, cases):
         if args.no_tune:
-            tiles.append(None)
+            if p.K > 0:
+                p.set_tile(args.tile)
+            tiles.append(p.tile())
             continue
-        tile, _ = autotune.tune(p, p.new_vector(x0), steps=32)
+        tile, _ = autotune.tune(p, p.new_vector(x0), steps=32, batch=True)
         tiles.append(tile)
     tune_s = time.perf_counter() - t0
     opts = qg.solve_opts(args.steps, [3e-3] * 6, alphaf=[1e-5] * 6, n_total=args.steps,

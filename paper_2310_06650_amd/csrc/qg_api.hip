@@ -921,71 +921,120 @@ qg_status qg_solve(qg_problem* pr, double* d_x, double* d_m, double* d_v,
   return QG_OK;
 }
 
-qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x,
-                         double* const* d_m, double* const* d_v, void* const* d_workspace,
-                         const qg_solve_opts* o, const qg_adam_cfg* cfg, qg_solve_report* reps,
-                         void* stream) {
-  using clock = std::chrono::steady_clock;
-  if (n < 1 || n > QG_BATCH_MAX || !probs || !d_x || !d_m || !d_v || !d_workspace || !o ||
-      !cfg || !reps)
-    return fail(QG_ERR_ARG, "bad batch arguments");
-  qg_status s = check_solve_opts(o, cfg);
-  if (s != QG_OK) return s;
-  if (o->check_every != 0 || o->profile != 0)
-    return fail(QG_ERR_ARG, "batched solves take no gap checks and no profiling");
+// Common checks of a batch; fills the workspaces' device views.
+static qg_status check_batch(qg_problem* const* probs, int32_t n, double* const* d_x,
+                             double* const* d_m, double* const* d_v, void* const* d_workspace,
+                             std::vector<qg::DevWork>* w) {
+  if (n < 1 || n > QG_BATCH_MAX || !probs) return fail(QG_ERR_ARG, "bad batch size or problems");
   for (int i = 0; i < n; ++i) {
-    s = check_problem(probs[i]);
+    qg_status s = check_problem(probs[i]);
     if (s != QG_OK) return s;
-    if (!d_x[i] || !d_m[i] || !d_v[i] || !d_workspace[i] || !aligned(d_x[i]) ||
-        !aligned(d_m[i]) || !aligned(d_v[i]) || !aligned(d_workspace[i]))
-      return fail(QG_ERR_ARG, "null or misaligned buffer of scenario " + std::to_string(i));
     for (int j = 0; j < i; ++j)
       if (probs[j] == probs[i]) return fail(QG_ERR_ARG, "a problem appears twice in the batch");
     if (probs[i]->p.scr.on)
       return fail(QG_ERR_ARG, "batched solves score every contingency: turn screening off");
   }
-  const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
-  std::vector<qg::DevWork> w(n);
-  for (int i = 0; i < n; ++i) w[i] = qg::carve_workspace(&probs[i]->p, d_workspace[i]);
-  hipStream_t user = static_cast<hipStream_t>(stream);
-  hipStream_t ex = user ? user : probs[0]->own;
+  w->assign((size_t)n, qg::DevWork{});
+  if (!d_x) return QG_OK;  // sizing only
+  if (!d_m || !d_v || !d_workspace) return fail(QG_ERR_ARG, "null buffer arrays");
+  for (int i = 0; i < n; ++i) {
+    if (!d_x[i] || !d_m[i] || !d_v[i] || !d_workspace[i] || !aligned(d_x[i]) ||
+        !aligned(d_m[i]) || !aligned(d_v[i]) || !aligned(d_workspace[i]))
+      return fail(QG_ERR_ARG, "null or misaligned buffer of scenario " + std::to_string(i));
+    (*w)[i] = qg::carve_workspace(&probs[i]->p, d_workspace[i]);
+  }
+  return QG_OK;
+}
 
+static qg::EvalMode batch_mode(const qg_adam_cfg* cfg) {
   qg::EvalMode sm;
   std::memset(&sm, 0, sizeof(sm));
   sm.schedule = 1;
   sm.adam_b1 = cfg->beta1; sm.adam_b2 = cfg->beta2; sm.adam_eps = cfg->eps;
   sm.eps_in_num = cfg->eps_in_numerator;
+  return sm;
+}
 
-  // one graph of gsteps steps of every scenario: each scenario's steps on
-  // their own branch (its own stream during capture), joined at the end
+qg_status qg_batch_bytes(qg_problem* const* probs, int32_t n, size_t* bytes) {
+  if (!bytes) return fail(QG_ERR_ARG, "null output");
+  std::vector<qg::DevWork> w;
+  qg_status s = check_batch(probs, n, nullptr, nullptr, nullptr, nullptr, &w);
+  if (s != QG_OK) return s;
+  std::vector<const qg::Problem*> prs((size_t)n);
+  for (int i = 0; i < n; ++i) prs[i] = &probs[i]->p;
+  std::vector<const double*> xs((size_t)n, nullptr);
+  std::vector<double*> ms((size_t)n, nullptr);
+  qg_adam_cfg cfg{0.9, 0.999, 1e-8, 0};
+  qg::BatchPlan plan;
+  std::string err;
+  if (qg::plan_batch(prs.data(), w.data(), n, xs.data(), ms.data(), ms.data(), batch_mode(&cfg),
+                     &plan, nullptr, &err) != 0)
+    return fail(QG_ERR_ARG, err);
+  *bytes = plan.bytes;
+  return QG_OK;
+}
+
+qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x,
+                         double* const* d_m, double* const* d_v, void* const* d_workspace,
+                         void* d_batch, size_t batch_bytes, const qg_solve_opts* o,
+                         const qg_adam_cfg* cfg, qg_solve_report* reps, void* stream) {
+  using clock = std::chrono::steady_clock;
+  if (!d_x || !o || !cfg || !reps) return fail(QG_ERR_ARG, "null argument");
+  std::vector<qg::DevWork> w;
+  qg_status s = check_batch(probs, n, d_x, d_m, d_v, d_workspace, &w);
+  if (s != QG_OK) return s;
+  s = check_solve_opts(o, cfg);
+  if (s != QG_OK) return s;
+  if (o->check_every != 0 || o->profile != 0)
+    return fail(QG_ERR_ARG, "batched solves take no gap checks and no profiling");
+  if (o->reserved != 0) return fail(QG_ERR_ARG, "reserved field must be 0");
+  if (!d_batch || !aligned(d_batch)) return fail(QG_ERR_ARG, "batch buffer null or misaligned");
+  const int64_t n_total = o->n_total > 0 ? o->n_total : o->iter0 + o->n_steps;
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  hipStream_t ex = user ? user : probs[0]->own;
+  const qg::EvalMode sm = batch_mode(cfg);
+
+  // kernel arguments and block tables of every problem, in the batch buffer
+  std::vector<const qg::Problem*> prs((size_t)n);
+  std::vector<const double*> xs((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    prs[i] = &probs[i]->p;
+    xs[i] = d_x[i];
+  }
+  qg::BatchPlan plan;
+  std::vector<unsigned char> image;
+  std::string err;
+  if (qg::plan_batch(prs.data(), w.data(), n, xs.data(), d_m, d_v, sm, &plan, &image, &err) != 0)
+    return fail(QG_ERR_ARG, err);
+  if (batch_bytes < plan.bytes)
+    return fail(QG_ERR_ARG, "batch buffer too small: need " + std::to_string(plan.bytes));
+  HIP_TRY(hipMemcpyAsync(d_batch, image.data(), plan.bytes, hipMemcpyHostToDevice, ex),
+          "batch upload");
+  HIP_TRY(hipStreamSynchronize(ex), "sync");
+
+  // one graph of gsteps batched steps (six launches each)
   const int gsteps = (int)std::min<int64_t>(16, std::max<int64_t>(1, o->n_steps));
   hipGraphExec_t gexec = nullptr;
-  std::vector<hipEvent_t> evs(n + 1);
-  for (auto& e : evs) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  hipEvent_t ev[2] = {nullptr, nullptr};
   auto cleanup = [&]() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
-    for (auto& e : evs) (void)hipEventDestroy(e);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
   };
   {
     hipGraph_t g;
     hipStream_t cap = probs[0]->own;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = hipEventRecord(evs[n], cap);
-    for (int i = 0; i < n && e == hipSuccess; ++i) {
-      hipStream_t si = probs[i]->own;
-      if (i > 0) e = hipStreamWaitEvent(si, evs[n], 0);
-      for (int k = 0; k < gsteps && e == hipSuccess; ++k)
-        e = (hipError_t)qg::launch_eval(&probs[i]->p, w[i], d_x[i], nullptr, nullptr, sm, 1,
-                                        d_m[i], d_v[i], si, nullptr);
-      if (e == hipSuccess && i > 0) e = hipEventRecord(evs[i], si);
-      if (e == hipSuccess && i > 0) e = hipStreamWaitEvent(cap, evs[i], 0);
-    }
+    for (int k = 0; k < gsteps && e == hipSuccess; ++k)
+      e = (hipError_t)qg::launch_eval_batch(plan, d_batch, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) {
       e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
     }
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "batch graph capture"); }
   }
 
@@ -995,35 +1044,37 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
     probs[i]->p.sched_base = -1;
     probs[i]->p.sched_next = -1;
   }
+  hipError_t e = hipEventRecord(ev[0], ex);
+  if (e != hipSuccess) { cleanup(); return hip_fail(e, "event record"); }
   int64_t done = 0;
   while (done < o->n_steps) {
     const int64_t nc = std::min<int64_t>(o->n_steps - done, qg::kSchedCap);
     fill_schedule(table.data(), o, cfg, n_total, o->iter0 + done + 1, (int)nc);
     for (int i = 0; i < n; ++i) {
-      hipError_t e = hipMemcpyAsync(w[i].sched, table.data(),
-                                    (size_t)nc * qg::kSchedStride * sizeof(double),
-                                    hipMemcpyHostToDevice, ex);
+      e = hipMemcpyAsync(w[i].sched, table.data(), (size_t)nc * qg::kSchedStride * sizeof(double),
+                         hipMemcpyHostToDevice, ex);
       if (e == hipSuccess && qg::launch_set_step(&probs[i]->p, w[i], 0, ex) != 0)
         e = hipGetLastError();
       if (e != hipSuccess) { cleanup(); return hip_fail(e, "schedule upload"); }
     }
     int64_t left = nc;
     for (; left >= gsteps; left -= gsteps) {
-      hipError_t e = hipGraphLaunch(gexec, ex);
+      e = hipGraphLaunch(gexec, ex);
       if (e != hipSuccess) { cleanup(); return hip_fail(e, "graph launch"); }
     }
-    for (int i = 0; i < n; ++i)
-      for (int64_t k = 0; k < left; ++k)
-        if (qg::launch_eval(&probs[i]->p, w[i], d_x[i], nullptr, nullptr, sm, 1, d_m[i], d_v[i],
-                            ex, nullptr) != 0) {
-          cleanup();
-          return hip_fail(hipGetLastError(), "kernel launch");
-        }
+    for (; left > 0; --left)
+      if (qg::launch_eval_batch(plan, d_batch, ex) != 0) {
+        cleanup();
+        return hip_fail(hipGetLastError(), "kernel launch");
+      }
     done += nc;
   }
-  hipError_t e = hipStreamSynchronize(ex);
+  e = hipEventRecord(ev[1], ex);
+  if (e == hipSuccess) e = hipStreamSynchronize(ex);
   if (e != hipSuccess) { cleanup(); return hip_fail(e, "sync"); }
   const double wall = std::chrono::duration<double>(clock::now() - t_start).count();
+  float steps_ms = 0.f;
+  (void)hipEventElapsedTime(&steps_ms, ev[0], ev[1]);
   cleanup();
   // reports: the objective at the last schedule point and the score
   for (int i = 0; i < n; ++i) {
@@ -1033,6 +1084,12 @@ qg_status qg_solve_batch(qg_problem* const* probs, int32_t n, double* const* d_x
     r->steps_to_gap = -1;
     r->time_to_gap_s = -1.0;
     r->wall_s = wall;
+    r->steps_ms = steps_ms;
+    if (o->skip_final) {
+      r->final_loss = r->final_score = std::nan("");
+      for (double& t : r->terms) t = std::nan("");
+      continue;
+    }
     double last[QG_NTERMS];
     HIP_TRY(hipMemcpyAsync(last, w[i].terms, sizeof(last), hipMemcpyDeviceToHost, ex),
             "terms read");

@@ -279,6 +279,32 @@ int launch_adam(const Problem* p, double* x, double* m, double* v, const double*
                 const double lr[QG_NCLASS], double bc1, double bc2, double b1,
                 double b2, double eps, int eps_in_num, void* stream);
 int launch_set_step(const Problem* p, const DevWork& w, int64_t value, void* stream);
+
+// Batched step of independent problems: kStages launches for all of them.
+// The caller's batch buffer holds every problem's kernel arguments and, per
+// stage, a table of the launch's blocks (problem index << 22 | block of that
+// problem); stage 1, the contingency map-reduce, is a persistent launch that
+// takes its blocks' work items from a counter reset by stage 0.
+struct BatchPlan {
+  int n = 0;
+  int nblk[kStages] = {};      // blocks (stage 1: work items) of each batched launch
+  size_t off_args = 0;         // byte offsets into the batch buffer
+  size_t off_tab[kStages] = {};
+  size_t off_ctr = 0;
+  size_t bytes = 0;            // size of the batch buffer
+  int lodf_kind = 0;
+  int pm_grid = 0;             // blocks of the persistent map-reduce
+};
+constexpr int kBatchLocBits = 22;                  // block index bits of a table entry
+constexpr int kBatchWl = 4;                        // wavefronts per map-reduce block
+constexpr int kBatchTcw = 4;                       // periods per map-reduce wavefront
+// Sizes, validation and (image != nullptr) the host image of a batch buffer
+// for problems whose steps take x[i], m[i], v[i] and workspaces ws[i]; 0 or
+// a message in *err.
+int plan_batch(const Problem* const* prs, const DevWork* ws, int n, const double* const* x,
+               double* const* m, double* const* v, const EvalMode& mode, BatchPlan* plan,
+               std::vector<unsigned char>* image, std::string* err);
+int launch_eval_batch(const BatchPlan& plan, void* d_buf, void* stream);
 int launch_check_finite(const Problem* p, const double* x, int* flag, void* stream);
 // Screening (qg_screen.hip): choose the set from the severities of the last
 // exact evaluation (its z_tk and homotopy in the workspace), then gather its

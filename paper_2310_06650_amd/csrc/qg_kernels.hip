@@ -24,9 +24,14 @@
 // bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cfloat>
 #include <climits>
+#include <cstring>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "qg_internal.h"
 
@@ -763,11 +768,10 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
 
 // Blocks [0, nb_br): branch forward; [nb_br, nb_br + T): one period each;
 // then (Lp / 16) x (Tp / 16) flow slabs.
-__global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
-  __shared__ double smem[kSlabLds];
+__device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* smem) {
   StepParams sp;
   resolve_params(a, sp);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (b == 0 && threadIdx.x == 0) {
     double* pb = a.w.params;
     pb[PB_EPS] = sp.eps;
     pb[PB_BETA] = sp.beta;
@@ -776,13 +780,17 @@ __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
     pb[PB_BC1] = sp.bc1;
     pb[PB_BC2] = sp.bc2;
   }
-  const int b = blockIdx.x;
   if (b < a.nb_br)
     branch_forward(a, sp, b, smem);
   else if (b < a.nb_br + a.p.T)
     period_block(a, sp, b - a.nb_br, smem);
   else
     flow_slab(a, b - a.nb_br - a.p.T, smem);
+}
+
+__global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
+  __shared__ double smem[kSlabLds];
+  forward_body(a, blockIdx.x, smem);
 }
 
 // Per-(t, bus) power balance (Example 4): segmented sums of the bus's
@@ -1036,24 +1044,22 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
 // arithmetic keeps the exact test with F and qmax2 moved to SGPRs by
 // v_readlane from a per-tile lane load (lane e: period e / 8, branch e % 8).
 template <int TCW, typename LT>
-__global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
+__device__ __forceinline__ void ctg_pm_body(const EvalArgs& a, const LT* __restrict__ lodf,
+                                            int lb, int kb, int bz, int WL, double* dyn) {
   typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
   constexpr bool kF64 = std::is_same<R, double>::value;
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int WL = blockDim.x >> 6;
-  const int lb = blockIdx.x, kb = blockIdx.y;
   const int T = p.T, Lp = p.Lp, Kp = p.Kp;
-  const int tw = (blockIdx.z * WL + wv) * TCW;  // first period of the wavefront
+  const int tw = (bz * WL + wv) * TCW;  // first period of the wavefront
   const int ntw = min(TCW, T - tw);
   if (ntw <= 0) return;  // no barrier follows
   const int k = kb * 64 + lane;  // slot of the lane
   const int kc = a.act_k ? a.act_k[k] : k;
   // z and S of the wavefront's (period, lane) pairs live in its own slice
   // of LDS: only the per-branch path and the final store touch them
-  extern __shared__ double dyn[];
   double* zsh = dyn + (size_t)wv * TCW * 128;
   double* ssh = zsh + TCW * 64;
   R fk[TCW];
@@ -1226,6 +1232,12 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
   }
 }
 
+template <int TCW, typename LT>
+__global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
+  extern __shared__ double dyn[];
+  ctg_pm_body<TCW, LT>(a, lodf, blockIdx.x, blockIdx.y, blockIdx.z, blockDim.x >> 6, dyn);
+}
+
 // ---------------------------------------------------------------------------
 // K4: per-(t, k) penalties z_tk (the l-block partials plus the floor
 // (L-1) eps), the mean outage-correction derivative, and per 64-contingency
@@ -1236,10 +1248,10 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 constexpr int kZredBatch = 32;
 
 template <bool SPARSE>
-__global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
+__device__ __forceinline__ void ctg_zred_body(const EvalArgs& a, int kc, int t) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
-  const int t = blockIdx.y, kc = blockIdx.x, lane = threadIdx.x;
+  const int lane = threadIdx.x;
   const int T = p.T, L = p.L, K = p.K, Kp = p.Kp;
   const double eps = w.params[PB_EPS], beta = w.params[PB_BETA];
   const double kt = p.dt[t] * p.c_s * beta;
@@ -1295,6 +1307,11 @@ __global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
     w.zargp[c] = (double)idx;
     w.zsump[c] = tot;
   }
+}
+
+template <bool SPARSE>
+__global__ __launch_bounds__(64) void k_ctg_zred(EvalArgs a) {
+  ctg_zred_body<SPARSE>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1426,13 +1443,13 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
 // Blocks [0, nLc T): flow adjoints of (period, 256-branch chunk); then the
 // nb_bus power-balance blocks, which only need the forward flows.
 template <bool SPARSE>
-__global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
-  __shared__ double smem[2 * kSegChunk + 16];
-  const int b = blockIdx.x, nasm = a.nLc * a.p.T;
+__device__ __forceinline__ void ctg_asm_body(const EvalArgs& a, int b, int nblocks,
+                                             double* smem) {
+  const int nasm = a.nLc * a.p.T;
   // scheduled steps: the next step's schedule row (the counter is advanced
   // by k_final, after this kernel), clamped to the table; a new table comes
   // with k_set_step, which copies its own row
-  if (a.mode.schedule && b == (int)gridDim.x - 1 && threadIdx.x < kSchedStride) {
+  if (a.mode.schedule && b == nblocks - 1 && threadIdx.x < kSchedStride) {
     const int64_t s1 = min(a.w.step[0] + 1, (int64_t)kSchedCap - 1);
     a.w.snext[threadIdx.x] = a.w.sched[s1 * kSchedStride + threadIdx.x];
   }
@@ -1440,6 +1457,12 @@ __global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
     ctg_assemble<SPARSE>(a, b / a.nLc, b % a.nLc, smem);
   else
     bus_balance(a, b - nasm, smem);
+}
+
+template <bool SPARSE>
+__global__ __launch_bounds__(kBlock) void k_ctg_asm(EvalArgs a) {
+  __shared__ double smem[2 * kSegChunk + 16];
+  ctg_asm_body<SPARSE>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1484,12 +1507,11 @@ __device__ void branch_reverse(const EvalArgs& a, int blk) {
 // Blocks [0, nslab * nsplit): the DC part of dL/dp, one 16-generator slab and
 // one slice of the branch dimension each (partials summed in k_final); then
 // nb_br branch-reverse blocks; then the worst outage's ISF rows.
-__global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
-  __shared__ double smem[kSlabLds];
+__device__ __forceinline__ void adjoint_body(const EvalArgs& a, int bx, double* smem) {
   const DevProblem& p = a.p;
   const int nslab = p.G16 / 16;
-  if ((int)blockIdx.x < nslab * a.nsplit) {
-    const int slab = blockIdx.x % nslab, sp = blockIdx.x / nslab;
+  if (bx < nslab * a.nsplit) {
+    const int slab = bx % nslab, sp = bx / nslab;
     const int n0 = slab * 16;
     const int steps = p.Lp / 4;
     const int per = (steps + a.nsplit - 1) / a.nsplit;
@@ -1507,7 +1529,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
     mfma_slab_dispatch<8>(p.Tp / 16, aload, p.isf_ga, G16, k0, k1, n0, smem, epi);
     return;
   }
-  const int b = blockIdx.x - nslab * a.nsplit;
+  const int b = bx - nslab * a.nsplit;
   if (b < a.nb_br) {
     branch_reverse(a, b);
     return;
@@ -1520,6 +1542,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
     const int bks = p.brk[(int)a.w.kstar[t]];
     a.w.isfk[idx] = p.isf_ga[(size_t)bks * p.G16 + j];
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint(EvalArgs a) {
+  __shared__ double smem[kSlabLds];
+  adjoint_body(a, blockIdx.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1559,8 +1586,7 @@ __device__ __forceinline__ void adam_entry(double* x, double* m, double* v, size
   adam_store(x, m, v, e, adam_load(x, m, v, e), g, lr, lo, hi, c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
-  __shared__ double smem[2 * kSegChunk + 8 * kBlock];
+__device__ __forceinline__ void final_body(const EvalArgs& a, int bx, double* smem) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int tid = threadIdx.x;
@@ -1574,9 +1600,9 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     for (int c = 0; c < QG_NCLASS; ++c) alpha[c] = w.params[PB_ALPHA + c];
   }
   double* xm = const_cast<double*>(a.x);
-  if ((int)blockIdx.x < a.nb_bus) {
-    const int t = blockIdx.x / a.bus_chunks;
-    const int c = blockIdx.x - t * a.bus_chunks;
+  if (bx < a.nb_bus) {
+    const int t = bx / a.bus_chunks;
+    const int c = bx - t * a.bus_chunks;
     const int i0 = c * kBlock;
     const int nbus = min(kBlock, N - i0);
     const double* src[2] = {w.epGV + (size_t)t * p.twoL, w.epGT + (size_t)t * p.twoL};
@@ -1600,7 +1626,7 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     }
     return;
   }
-  const int gb = blockIdx.x - a.nb_bus;
+  const int gb = bx - a.nb_bus;
   if (gb < a.nb_gen) {
     // dL/dp: device partials, balance multiplier, and the DC part: the MFMA
     // split partials plus the worst contingency's rank-1 term
@@ -1668,6 +1694,11 @@ __global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
     }
     if (a.mode.schedule) w.step[0] = w.step[0] + 1;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_final(EvalArgs a) {
+  __shared__ double smem[2 * kSegChunk + 8 * kBlock];
+  final_body(a, blockIdx.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1870,6 +1901,217 @@ int launch_eval(const Problem* pr, const DevWork& w, const double* x, double* gr
     launch_stage(pr, a, i, s);
   }
   if (events) (void)hipEventRecord(static_cast<hipEvent_t>(events[kStages]), s);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: the same six stages for many independent problems, one launch
+// per stage.  A block finds its problem and its block of that problem in the
+// stage's table (one scalar load); the kernel arguments of every problem sit
+// in the batch buffer.  Each problem's blocks do exactly what they do in a
+// launch of its own, so a batched step gives bitwise the points of the
+// problems' own steps.
+
+__device__ __forceinline__ void batch_entry(const uint32_t* __restrict__ tab, uint32_t i, int& s,
+                                            int& loc) {
+  const uint32_t e = tab[i];
+  s = (int)(e >> kBatchLocBits);
+  loc = (int)(e & ((1u << kBatchLocBits) - 1u));
+}
+
+__global__ __launch_bounds__(kBlock) void k_forward_b(const EvalArgs* __restrict__ args,
+                                                      const uint32_t* __restrict__ tab, int* ctr) {
+  __shared__ double smem[kSlabLds];
+  // the work counter of this step's map-reduce (the previous step's has
+  // finished: the launches are ordered)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ctr = 0;
+  int s, b;
+  batch_entry(tab, blockIdx.x, s, b);
+  forward_body(args[s], b, smem);
+}
+
+// Persistent contingency map-reduce: every block takes work items (one
+// period-split block of one problem: l-block, k-block, period chunk) from the
+// counter until none is left.  Items are ordered by decreasing work, so the
+// last ones to be taken are short.  Tiles: 4 wavefronts of 4 periods (the
+// problem's tile), its branch tiles per block free.
+template <typename LT>
+__global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __restrict__ args,
+                                                            const uint32_t* __restrict__ items,
+                                                            int nitems, int* ctr) {
+  extern __shared__ double dyn[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();  // every wave has read the item before it is replaced
+    if (it >= nitems) break;
+    int s, loc;
+    batch_entry(items, (uint32_t)it, s, loc);
+    const EvalArgs& a = args[s];
+    const int nLb = a.nLb, nKb = a.nKb;
+    const int lb = loc % nLb, kb = (loc / nLb) % nKb, bz = loc / (nLb * nKb);
+    ctg_pm_body<kBatchTcw, LT>(a, static_cast<const LT*>(a.lodf_sel), lb, kb, bz, kBatchWl, dyn);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_ctg_zred_b(const EvalArgs* __restrict__ args,
+                                                   const uint32_t* __restrict__ tab) {
+  int s, b;
+  batch_entry(tab, blockIdx.x, s, b);
+  const EvalArgs& a = args[s];
+  ctg_zred_body<true>(a, b % a.nKc, b / a.nKc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctg_asm_b(const EvalArgs* __restrict__ args,
+                                                      const uint32_t* __restrict__ tab) {
+  __shared__ double smem[2 * kSegChunk + 16];
+  int s, b;
+  batch_entry(tab, blockIdx.x, s, b);
+  const EvalArgs& a = args[s];
+  ctg_asm_body<true>(a, b, a.nLc * a.p.T + a.nb_bus, smem);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint_b(const EvalArgs* __restrict__ args,
+                                                      const uint32_t* __restrict__ tab) {
+  __shared__ double smem[kSlabLds];
+  int s, b;
+  batch_entry(tab, blockIdx.x, s, b);
+  adjoint_body(args[s], b, smem);
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_b(const EvalArgs* __restrict__ args,
+                                                    const uint32_t* __restrict__ tab) {
+  __shared__ double smem[2 * kSegChunk + 8 * kBlock];
+  int s, b;
+  batch_entry(tab, blockIdx.x, s, b);
+  final_body(args[s], b, smem);
+}
+
+// Blocks of each stage of one problem (stage 1: map-reduce work items).
+static void stage_blocks(const Problem* pr, const EvalArgs& a, int out[kStages]) {
+  const int span = pr->tile.wl * pr->tile.tc;
+  out[0] = pr->nb_br + pr->T + pr->Lp / 16 * (pr->Tp / 16);
+  out[1] = pr->K > 0 ? pr->nLb * a.nKb * ((pr->T + span - 1) / span) : 0;
+  out[2] = pr->K > 0 ? a.nKc * pr->T : 0;
+  out[3] = pr->nLc * pr->T + pr->nb_bus;
+  out[4] = pr->G16 / 16 * pr->nsplit + pr->nb_br + (pr->T * pr->G16 + kBlock - 1) / kBlock;
+  out[5] = pr->nb_bus + pr->nb_gen + 1;
+}
+
+static size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int plan_batch(const Problem* const* prs, const DevWork* ws, int n, const double* const* x,
+               double* const* m, double* const* v, const EvalMode& mode, BatchPlan* plan,
+               std::vector<unsigned char>* image, std::string* err) {
+  BatchPlan P;
+  P.n = n;
+  std::vector<EvalArgs> args((size_t)n);
+  std::vector<std::array<int, kStages>> nb((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const Problem* pr = prs[i];
+    const CtgTile& t = pr->tile;
+    if (pr->K > 0 && !(t.split && t.wl == kBatchWl && t.tc == kBatchTcw)) {
+      *err = "problem " + std::to_string(i) +
+             ": the batched step needs a period-split tile of 4 wavefronts of 4 periods";
+      return 1;
+    }
+    if (pr->scr.on) {
+      *err = "problem " + std::to_string(i) + ": screening is not supported in a batch";
+      return 1;
+    }
+    if (i > 0 && pr->dp.lodf_kind != prs[0]->dp.lodf_kind) {
+      *err = "every problem of a batch needs the same storage of the outage factors";
+      return 1;
+    }
+    args[i] = make_args(pr, ws[i], x[i], nullptr, nullptr, mode, 1, m[i], v[i]);
+    int b[kStages];
+    stage_blocks(pr, args[i], b);
+    for (int q = 0; q < kStages; ++q) {
+      if (b[q] >= (1 << kBatchLocBits)) {
+        *err = "problem " + std::to_string(i) + " has too many blocks for a batch";
+        return 1;
+      }
+      nb[i][q] = b[q];
+      P.nblk[q] += b[q];
+    }
+  }
+  P.lodf_kind = n > 0 ? prs[0]->dp.lodf_kind : 0;
+  size_t o = 0;
+  P.off_args = o;
+  o = align_up(o + (size_t)n * sizeof(EvalArgs));
+  for (int q = 0; q < kStages; ++q) {
+    P.off_tab[q] = o;
+    o = align_up(o + (size_t)P.nblk[q] * sizeof(uint32_t));
+  }
+  P.off_ctr = o;
+  o = align_up(o + sizeof(int));
+  P.bytes = o;
+  if (image) {
+    image->assign(P.bytes, 0);
+    std::memcpy(image->data() + P.off_args, args.data(), (size_t)n * sizeof(EvalArgs));
+    // map-reduce items: problems by decreasing work per item (periods and
+    // branch tiles of a block), each problem's items in its grid order
+    std::vector<int> order((size_t)n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto item_work = [&](int i) {
+      const Problem* pr = prs[i];
+      return (int64_t)std::min(pr->T, kBatchWl * pr->tile.tc) * pr->tile.lt;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a2, int b2) { return item_work(a2) > item_work(b2); });
+    for (int q = 0; q < kStages; ++q) {
+      uint32_t* tab = reinterpret_cast<uint32_t*>(image->data() + P.off_tab[q]);
+      size_t k = 0;
+      for (int j = 0; j < n; ++j) {
+        const int i = q == 1 ? order[j] : j;
+        for (int b = 0; b < nb[i][q]; ++b)
+          tab[k++] = ((uint32_t)i << kBatchLocBits) | (uint32_t)b;
+      }
+    }
+  }
+  // persistent map-reduce: as many blocks as fit on the chip at once
+  int dev = 0, ncu = 256, per_cu = 1;
+  const size_t lds = (size_t)kBatchWl * kBatchTcw * 128 * sizeof(double);
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  hipError_t e;
+  if (P.lodf_kind == kLodfF64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double>, kBatchWl * 64, lds);
+  else if (P.lodf_kind == kLodfF32)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<float>, kBatchWl * 64, lds);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<uint16_t>, kBatchWl * 64,
+                                                     lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  P.pm_grid = std::max(1, std::min(P.nblk[1], ncu * per_cu));
+  *plan = P;
+  return 0;
+}
+
+int launch_eval_batch(const BatchPlan& P, void* d_buf, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* b = static_cast<unsigned char*>(d_buf);
+  const EvalArgs* args = reinterpret_cast<const EvalArgs*>(b + P.off_args);
+  auto tab = [&](int q) { return reinterpret_cast<const uint32_t*>(b + P.off_tab[q]); };
+  int* ctr = reinterpret_cast<int*>(b + P.off_ctr);
+  hipLaunchKernelGGL(k_forward_b, dim3(P.nblk[0]), dim3(kBlock), 0, s, args, tab(0), ctr);
+  if (P.nblk[1] > 0) {
+    const size_t lds = (size_t)kBatchWl * kBatchTcw * 128 * sizeof(double);
+    const dim3 g(P.pm_grid), blk(kBatchWl * 64);
+    if (P.lodf_kind == kLodfF64)
+      hipLaunchKernelGGL(k_ctg_pm_b<double>, g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+    else if (P.lodf_kind == kLodfF32)
+      hipLaunchKernelGGL(k_ctg_pm_b<float>, g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+    else
+      hipLaunchKernelGGL(k_ctg_pm_b<uint16_t>, g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+  }
+  if (P.nblk[2] > 0)
+    hipLaunchKernelGGL(k_ctg_zred_b, dim3(P.nblk[2]), dim3(64), 0, s, args, tab(2));
+  hipLaunchKernelGGL(k_ctg_asm_b, dim3(P.nblk[3]), dim3(kBlock), 0, s, args, tab(3));
+  hipLaunchKernelGGL(k_adjoint_b, dim3(P.nblk[4]), dim3(kBlock), 0, s, args, tab(4));
+  hipLaunchKernelGGL(k_final_b, dim3(P.nblk[5]), dim3(kBlock), 0, s, args, tab(5));
   return (int)hipGetLastError();
 }
 

@@ -153,9 +153,11 @@ _sig = {
     "qg_solve": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(qg_solve_opts),
                            C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp, _vp]),
     "qg_debug_fetch": (C.c_int, [_vp, _vp, C.c_char_p, _vp, C.c_size_t, _vp]),
+    "qg_batch_bytes": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(C.c_size_t)]),
     "qg_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
-                                 C.POINTER(_vp), C.POINTER(_vp), C.POINTER(qg_solve_opts),
-                                 C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp]),
+                                 C.POINTER(_vp), C.POINTER(_vp), _vp, C.c_size_t,
+                                 C.POINTER(qg_solve_opts), C.POINTER(qg_adam_cfg),
+                                 C.POINTER(qg_solve_report), _vp]),
     "qg_screen_bytes": (C.c_int, [_vp, C.POINTER(qg_screen_opts), C.POINTER(C.c_size_t)]),
     "qg_set_screening": (C.c_int, [_vp, C.POINTER(qg_screen_opts), _vp, C.c_size_t, _vp]),
     "qg_screen_refresh": (C.c_int, [_vp, _vp, C.POINTER(qg_homotopy), C.c_int64, _vp, _vp]),
@@ -626,6 +628,19 @@ class MLP:
         return out
 
 
+def batch_bytes(problems):
+    """qg_batch_bytes: device bytes of the batch buffer of these problems."""
+    n = len(problems)
+    out = C.c_size_t(0)
+    _check(lib.qg_batch_bytes((_vp * n)(*[C.c_void_p(p.handle.value) for p in problems]), n,
+                              C.byref(out)), "qg_batch_bytes")
+    return int(out.value)
+
+
+# batch buffers by device, grown as needed (caller-owned device memory)
+_batch_bufs = {}
+
+
 def solve_batch(problems, xs, ms, vs, opts, cfg=None, stream=None):
     """qg_solve_batch over Problem objects and their device vectors; returns
     the per-scenario reports."""
@@ -635,9 +650,16 @@ def solve_batch(problems, xs, ms, vs, opts, cfg=None, stream=None):
     reps = (qg_solve_report * n)()
     cfg = cfg or adam_cfg()
     st = stream if stream is not None else torch.cuda.current_stream()
+    need = batch_bytes(problems)
+    dev = problems[0].device
+    buf = _batch_bufs.get(str(dev))
+    if buf is None or buf.numel() < need:
+        buf = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        _batch_bufs[str(dev)] = buf
     _check(lib.qg_solve_batch(arr([p.handle.value for p in problems]), n,
                               arr([x.data_ptr() for x in xs]), arr([m.data_ptr() for m in ms]),
                               arr([v.data_ptr() for v in vs]),
-                              arr([p.workspace.data_ptr() for p in problems]), C.byref(opts),
+                              arr([p.workspace.data_ptr() for p in problems]),
+                              C.c_void_p(buf.data_ptr()), buf.numel(), C.byref(opts),
                               C.byref(cfg), reps, C.c_void_p(st.cuda_stream)), "qg_solve_batch")
     return list(reps)

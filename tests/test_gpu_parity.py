@@ -545,20 +545,30 @@ def test_update_loads_matches_fresh_build(qg):
     assert np.array_equal(outs[0], outs[1])
 
 
+def _batch_tile(qg, p, c):
+    if p.K > 0:
+        p.set_tile("s4x4x2" if c.n_period < 32 else "s4x4x4")
+
+
 def test_batched_solve_matches_single_solves(qg):
-    """Scenarios of different sizes solved together in one graph end where
-    each one solved alone ends, bit for bit."""
+    """Scenarios of different sizes solved together (six launches per step
+    for the whole batch, the map-reduce persistent over a work list) end
+    where each one solved alone ends, bit for bit; also with an odd step
+    count (a graph of 16 steps and plain launches) and a radial scenario
+    without contingencies in the batch."""
     import torch
-    cases = synth.batch_cases(3, seed0=77, n_bus=(30, 120), n_period=(4, 12))
-    opts = qg.solve_opts(40, [1e-3] * 6, alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3, use_graph=1)
+    cases = synth.batch_cases(3, seed0=77, n_bus=(30, 120), n_period=(4, 40))
+    cases.append(tiny_case(5, [0, 1, 2, 1], [1, 2, 3, 4], [0.1, 0.2, 0.1, 0.15], [0, 3], T=3))
+    opts = qg.solve_opts(37, [1e-3] * 6, alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3, use_graph=1)
     alone, probs, xs, ms, vs = [], [], [], [], []
     for c in cases:
         p = qg.Problem(c)
+        _batch_tile(qg, p, c)
         x0 = synth.flat_start(c)
         x, m, v = p.new_vector(x0), p.new_vector(), p.new_vector()
         p.solve(x, m, v, opts)
         torch.cuda.synchronize()
-        alone.append(x.cpu().numpy().copy())
+        alone.append((x.cpu().numpy().copy(), m.cpu().numpy().copy()))
         x.copy_(torch.from_numpy(x0).to(x.device))
         m.zero_()
         v.zero_()
@@ -566,11 +576,66 @@ def test_batched_solve_matches_single_solves(qg):
         xs.append(x)
         ms.append(m)
         vs.append(v)
+    assert probs[-1].K == 0
     reps = qg.solve_batch(probs, xs, ms, vs, opts)
     torch.cuda.synchronize()
-    for a, x, r in zip(alone, xs, reps):
+    for (a, am), x, m, r in zip(alone, xs, ms, reps):
         assert np.array_equal(a, x.cpu().numpy())
-        assert r.steps_done == 40 and np.isfinite(r.final_score)
+        assert np.array_equal(am, m.cpu().numpy())
+        assert r.steps_done == 37 and np.isfinite(r.final_score) and r.steps_ms > 0.0
+    # a tile the batched step does not take is refused
+    probs[0].set_tile("8x8x4")
+    with pytest.raises(qg.QgError):
+        qg.solve_batch(probs, xs, ms, vs, opts)
+
+
+def test_batched_steps_match_oracle_uneven_sizes(qg):
+    """Four scenarios spanning the batch range (100 to 2,000 buses, 12 to 48
+    periods, every non-islanding outage) take two batched steps from seeded
+    interior points: the gradient each scenario's first step used (recovered
+    from the first Adam moment, m_1 = (1 - beta1) g) and the points after one
+    and two steps match the FP64 oracle (normwise per variable class, 1e-9)."""
+    import torch
+    shapes = [(100, 12), (640, 20), (1300, 33), (2000, 48)]
+    cases = [synth.make_case(seed=4100 + i, n_bus=nb, n_branch=int(round(1.4 * nb)),
+                             n_gen=max(2, int(round(0.15 * nb))), n_period=T, n_ctg=None,
+                             tree="prufer", mesh=3.0, name=f"b{i}")
+             for i, (nb, T) in enumerate(shapes)]
+    n = 2
+    sopt = _sched_opts(n, [1e-3] * 6, [1e-3] * 6)
+    common = dict(n_total=n, eps0=sopt["eps0"], epsf=sopt["epsf"], beta0=0.5, betaf=1.0,
+                  rho0=0.5, rhof=1.0, use_graph=1)
+    probs, xs, ms, vs, x0s = [], [], [], [], []
+    for i, c in enumerate(cases):
+        p = qg.Problem(c)
+        _batch_tile(qg, p, c)
+        x0 = synth.random_point(c, 50 + i)
+        probs.append(p)
+        x0s.append(x0)
+        xs.append(p.new_vector(x0))
+        ms.append(p.new_vector())
+        vs.append(p.new_vector())
+    qg.solve_batch(probs, xs, ms, vs, qg.solve_opts(1, [1e-3] * 6, iter0=0, **common))
+    torch.cuda.synchronize()
+    x1 = [x.cpu().numpy().copy() for x in xs]
+    m1 = [m.cpu().numpy().copy() for m in ms]
+    qg.solve_batch(probs, xs, ms, vs, qg.solve_opts(1, [1e-3] * 6, iter0=1, **common))
+    torch.cuda.synchronize()
+    for c, x0, xa, ma, xb in zip(cases, x0s, x1, m1, xs):
+        model = oracle_model(c)
+        lo, hi = oadam.box_bounds(c)
+        state = (x0, np.zeros_like(x0), np.zeros_like(x0))
+        for i in range(n):
+            eps, beta, rho, alpha = osolve.schedule(i + 1, n, sopt)
+            _, g = ob.evaluate(model, state[0], eps, beta, rho)
+            if i == 0:
+                gb = ma / (1.0 - 0.9)
+                assert_grad_close(c, gb, g, tol=1e-9)
+            state = oadam.adam_update(*state, g, i + 1, osolve.class_vector(c, alpha), lo, hi)
+            got = xa if i == 0 else xb.cpu().numpy()
+            for sl in c.block_slices():
+                ref = state[0][sl]
+                assert np.abs(got[sl] - ref).max() <= 1e-9 * np.abs(ref).max(), (c.name, i)
 
 
 def test_autotuner_picks_a_timed_tile_and_caches_it(qg, tmp_path, monkeypatch):
