@@ -217,7 +217,18 @@ qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
                            void* d_const_arena, size_t const_bytes, void* stream,
                            qg_problem** out);
 
-/* Offsets and lengths of the six blocks of x. */
+/*
+ * The host part of qg_build_problem alone: validates the description, finds
+ * the contingency set, factors the reduced susceptance matrix (eq.
+ * (Yb_solve)), forms the shift factors (eq. (p_flow)) and outage factors
+ * (eq. (rank_correct)), and writes the constant arena's image into
+ * host_image (caller-owned host memory of at least const_bytes bytes; the
+ * bytes qg_build_problem uploads).  No device work.
+ * Errors: ARG, TOPOLOGY, SINGULAR.
+ */
+qg_status qg_build_image(const qg_grid_desc* desc, const qg_build_opts* opts, void* host_image,
+                         size_t bytes);
+
 /*
  * New loads on the same grid (warm-start workflows: the topology, the factor
  * and the outage factors are kept): load_p, load_q [T*N] period-major and
@@ -230,6 +241,7 @@ qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
 qg_status qg_update_loads(qg_problem* prob, const double* load_p, const double* load_q,
                           const double* reserve_req, void* stream);
 
+/* Offsets and lengths of the six blocks of x. */
 qg_status qg_layout_of(const qg_problem* prob, qg_layout* out);
 
 /* Copy the contingency list actually used (K entries) into host memory. */

@@ -200,6 +200,21 @@ qg_status qg_build_problem(const qg_grid_desc* desc, const qg_build_opts* opts,
   return QG_OK;
 }
 
+qg_status qg_build_image(const qg_grid_desc* desc, const qg_build_opts* opts, void* host_image,
+                         size_t bytes) {
+  if (!host_image) return fail(QG_ERR_ARG, "null host image");
+  qg::Problem p;
+  qg_status s = qg::plan_problem(desc, opts, &p);
+  if (s != QG_OK) return s;
+  if (bytes < p.const_bytes)
+    return fail(QG_ERR_ARG, "host image too small: need " + std::to_string(p.const_bytes));
+  qg::HostBuild hb;
+  s = qg::build_arena(desc, opts, &p, &hb);
+  if (s != QG_OK) return s;
+  std::memcpy(host_image, hb.image.data(), hb.image.size());
+  return QG_OK;
+}
+
 qg_status qg_update_loads(qg_problem* pr, const double* load_p, const double* load_q,
                           const double* reserve_req, void* stream) {
   qg_status s = check_problem(pr);

@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqg.so")
+# QG_LIBRARY names another build of the same library (the host-sanitized one
+# of build.build(sanitize=True)); by default the in-tree libqg.so
+LIB_PATH = os.environ.get("QG_LIBRARY") or os.path.join(_HERE, "libqg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -154,6 +156,8 @@ _sig = {
                            C.POINTER(qg_adam_cfg), C.POINTER(qg_solve_report), _vp, _vp]),
     "qg_debug_fetch": (C.c_int, [_vp, _vp, C.c_char_p, _vp, C.c_size_t, _vp]),
     "qg_batch_bytes": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(C.c_size_t)]),
+    "qg_build_image": (C.c_int, [C.POINTER(qg_grid_desc), C.POINTER(qg_build_opts), _vp,
+                                 C.c_size_t]),
     "qg_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
                                  C.POINTER(_vp), C.POINTER(_vp), _vp, C.c_size_t,
                                  C.POINTER(qg_solve_opts), C.POINTER(qg_adam_cfg),
@@ -253,6 +257,14 @@ def build_opts(case=None, ctg_mode=QG_CTG_LIST, ctg_list=None, ref_bus=None, fla
 def qg_problem_sizes(desc, opts):
     out = qg_sizes()
     _check(lib.qg_problem_sizes(C.byref(desc), C.byref(opts), C.byref(out)), "qg_problem_sizes")
+    return out
+
+
+def qg_build_image(desc, opts, nbytes):
+    """The constant arena's image, built on the host (numpy uint8 array)."""
+    out = np.zeros(max(int(nbytes), 1), dtype=np.uint8)
+    _check(lib.qg_build_image(C.byref(desc), C.byref(opts), out.ctypes.data_as(_vp),
+                              out.nbytes), "qg_build_image")
     return out
 
 

@@ -158,3 +158,43 @@ def test_sum_flag_and_period_limit():
     with pytest.raises(qg.QgError) as e:
         _sizes(c65)
     assert e.value.status == qg.QG_ERR_ARG
+
+
+def _image(case, mode=None, ctg=None):
+    desc, k1 = qg.grid_desc(case)
+    opts, k2 = qg.build_opts(case, ctg_mode=qg.QG_CTG_LIST if mode is None else mode,
+                             ctg_list=ctg)
+    sizes = qg.qg_problem_sizes(desc, opts)
+    return qg.qg_build_image(desc, opts, sizes.const_bytes), sizes
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_host_build_image_is_deterministic(name):
+    """The host part of the build (bridges, factor, shift and outage factors)
+    fills the arena image the same way twice, to the last byte."""
+    c = synth.config_case(name)
+    a, sizes = _image(c)
+    b, _ = _image(c)
+    assert a.size == sizes.const_bytes
+    assert np.array_equal(a, b)
+    assert np.count_nonzero(a) > a.size // 10
+
+
+def test_host_build_image_errors():
+    c = synth.config_case("c1")
+    desc, k1 = qg.grid_desc(c)
+    opts, k2 = qg.build_opts(c)
+    sizes = qg.qg_problem_sizes(desc, opts)
+    with pytest.raises(qg.QgError) as ei:
+        qg.qg_build_image(desc, opts, sizes.const_bytes - 1)
+    assert ei.value.status == qg.QG_ERR_ARG
+    # an outage that islands (a radial branch) in the list
+    radial = tiny_case(4, [0, 1, 2, 0], [1, 2, 0, 3], [0.1, 0.2, 0.1, 0.1], [0, 1])
+    with pytest.raises(qg.QgError) as ei:
+        _image(radial, ctg=[3])
+    assert ei.value.status == qg.QG_ERR_TOPOLOGY
+    # a disconnected grid
+    split = tiny_case(4, [0, 2], [1, 3], [0.1, 0.1], [0, 2])
+    with pytest.raises(qg.QgError) as ei:
+        _image(split)
+    assert ei.value.status == qg.QG_ERR_TOPOLOGY

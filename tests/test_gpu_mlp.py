@@ -72,6 +72,36 @@ def test_forward_loss_and_gradient(qg, shape):
         assert rel(g[bo:bo + db.size], db) < 2e-5, ("b", i)
 
 
+# the network of the learned warm start: 617-bus x 18-period loads and
+# reserves in, 3 x 512 GELU, every variable of the grid out, batch 64
+C5_SHAPE = (11124, 512, 3, 29412, 64)
+
+
+def test_forward_loss_and_gradient_c5_shape(qg):
+    """The real warm-start network.  Products of up to 11,124 FP32 terms carry
+    about sqrt(11124) 2^-24 = 6e-6 relative error per output, and the reverse
+    pass chains four layers: outputs, loss and every gradient array are
+    compared at 1e-4 normwise; the BF16 forward at 3e-2."""
+    import torch
+    net, params, x, t, xd, td = make(qg, *C5_SHAPE, seed=11)
+    y = net.forward(xd)
+    torch.cuda.synchronize()
+    y_ref = omlp.forward(params, x)
+    assert rel(y.cpu().numpy(), y_ref) < 1e-4
+    g, loss = net.grad_and_loss(xd, td)
+    torch.cuda.synchronize()
+    loss_ref, grads_ref = omlp.loss_and_grad(params, x, t)
+    assert abs(float(loss) - loss_ref) <= 1e-4 * loss_ref
+    g = g.cpu().numpy()
+    for i, (dW, db) in enumerate(grads_ref):
+        wo, bo = net.offsets(i)
+        assert rel(g[wo:wo + dW.size].reshape(dW.shape), dW) < 1e-4, ("W", i)
+        assert rel(g[bo:bo + db.size], db) < 1e-4, ("b", i)
+    y16 = net.forward_bf16(xd)
+    torch.cuda.synchronize()
+    assert rel(y16.cpu().numpy(), y_ref) < 3e-2
+
+
 def test_train_step_is_grad_then_adam(qg):
     import torch
     net, params, x, t, xd, td = make(qg, 37, 48, 3, 53, 19, seed=5)
