@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--no-gap", action="store_true",
                     help="skip the time-to-gap measurement of the plain solve")
     ap.add_argument("--gap-steps", type=int, default=20000)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain time-to-gap leg")
+    ap.add_argument("--learned-train", type=int, default=128)
+    ap.add_argument("--learned-test", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this size "
                          "(calibrates the byte counters of a profile)")
@@ -154,6 +158,35 @@ def plain_gap(qg, synth, prob, case, n_steps):
                 start="flat (v = 1, theta = 0, u = 1, proportional p)",
                 schedule="alpha 3e-3 -> 1e-5, eps 1e-1 -> 1e-4, beta and rho scale 0.1 -> 1",
                 note="score checked every 250 steps; times exclude the LP")
+
+
+def learned_gap(case, n_train, n_test, solve_steps, train_steps):
+    """The learned half of the metric on a bounded sample: the warm-start
+    pipeline of paper_2310_06650_amd.warmstart (training days solved by the
+    batched plain solve, the network trained on them, held-out days started
+    from four points under the same schedules) with n_train training and
+    n_test held-out days; medians of the seconds to the 1 % target."""
+    from paper_2310_06650_amd import warmstart as wsm
+    t0 = time.perf_counter()
+    X, Y = wsm.generate(case, list(range(10000, 10000 + n_train)), solve_steps)
+    t1 = time.perf_counter()
+    ws = wsm.WarmStart(case, X, Y)
+    losses = ws.train(train_steps)
+    t2 = time.perf_counter()
+    rows = wsm.compare(case, ws, list(range(20000, 20000 + n_test)))
+    t3 = time.perf_counter()
+    by = wsm.summarise(rows)
+    med = {k: v["median_s"] for k, v in by.items()}
+    plain, net = med.get("flat/plain"), med.get("net/warm")
+    return dict(
+        sample=f"{n_train} training days ({solve_steps}-step plain solves, batched), network "
+               f"{X.shape[1]}-512x3-{Y.shape[1]} trained {train_steps} steps, {n_test} held-out "
+               f"days; target 0.99 x the plain solve's score after 20000 steps",
+        median_s_to_target=med,
+        reached={k: v["reached"] for k, v in by.items()},
+        plain_over_learned=(plain / net) if plain and net else None,
+        loss_first=losses[0], loss_last=losses[-1],
+        seconds=dict(data=t1 - t0, train=t2 - t1, compare=t3 - t2))
 
 
 def cpu_baseline(case, seconds):
@@ -289,6 +322,8 @@ def main():
                final_score=rep_p.final_score, roofline=roof)
     if not args.no_gap:
         out["gap"] = plain_gap(qg, synth, prob, case, args.gap_steps)
+    if not args.no_learned and args.config == "c2":
+        out["learned_gap"] = learned_gap(case, args.learned_train, args.learned_test, 8000, 800)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda:0")

@@ -1043,23 +1043,31 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
 // and thr_tl reach SGPRs by scalar loads issued one period ahead.  FP32
 // arithmetic keeps the exact test with F and qmax2 moved to SGPRs by
 // v_readlane from a per-tile lane load (lane e: period e / 8, branch e % 8).
+//
+// The batched launch (k_ctg_pm_b) runs the same block code for each work
+// item; it is written out in both kernels rather than shared through an
+// inlined function, which made the compiler spill about three times as many
+// SGPRs and the map-reduce 1.5x slower.  Batched and single steps are checked
+// to agree bit for bit.
 template <int TCW, typename LT>
-__device__ __forceinline__ void ctg_pm_body(const EvalArgs& a, const LT* __restrict__ lodf,
-                                            int lb, int kb, int bz, int WL, double* dyn) {
+__global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
   typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
   constexpr bool kF64 = std::is_same<R, double>::value;
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int WL = blockDim.x >> 6;
+  const int lb = blockIdx.x, kb = blockIdx.y;
   const int T = p.T, Lp = p.Lp, Kp = p.Kp;
-  const int tw = (bz * WL + wv) * TCW;  // first period of the wavefront
+  const int tw = (blockIdx.z * WL + wv) * TCW;  // first period of the wavefront
   const int ntw = min(TCW, T - tw);
   if (ntw <= 0) return;  // no barrier follows
   const int k = kb * 64 + lane;  // slot of the lane
   const int kc = a.act_k ? a.act_k[k] : k;
   // z and S of the wavefront's (period, lane) pairs live in its own slice
   // of LDS: only the per-branch path and the final store touch them
+  extern __shared__ double dyn[];
   double* zsh = dyn + (size_t)wv * TCW * 128;
   double* ssh = zsh + TCW * 64;
   R fk[TCW];
@@ -1232,11 +1240,6 @@ __device__ __forceinline__ void ctg_pm_body(const EvalArgs& a, const LT* __restr
   }
 }
 
-template <int TCW, typename LT>
-__global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
-  extern __shared__ double dyn[];
-  ctg_pm_body<TCW, LT>(a, lodf, blockIdx.x, blockIdx.y, blockIdx.z, blockDim.x >> 6, dyn);
-}
 
 // ---------------------------------------------------------------------------
 // K4: per-(t, k) penalties z_tk (the l-block partials plus the floor
@@ -1932,7 +1935,9 @@ __global__ __launch_bounds__(kBlock) void k_forward_b(const EvalArgs* __restrict
 
 // Persistent contingency map-reduce: every block takes work items (one
 // period-split block of one problem: l-block, k-block, period chunk) from the
-// counter until none is left.  Items are ordered by decreasing work, so the
+// counter until none is left, and runs k_ctg_pm's block code on each (a
+// wavefront without periods skips it, as every wavefront must reach the
+// barriers of the loop).  Items are ordered by decreasing work, so the
 // last ones to be taken are short.  Tiles: 4 wavefronts of 4 periods (the
 // problem's tile), its branch tiles per block free.
 template <typename LT>
@@ -1952,7 +1957,197 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
     const EvalArgs& a = args[s];
     const int nLb = a.nLb, nKb = a.nKb;
     const int lb = loc % nLb, kb = (loc / nLb) % nKb, bz = loc / (nLb * nKb);
-    ctg_pm_body<kBatchTcw, LT>(a, static_cast<const LT*>(a.lodf_sel), lb, kb, bz, kBatchWl, dyn);
+    constexpr int TCW = kBatchTcw;
+    const int WL = kBatchWl;
+    const LT* __restrict__ lodf = static_cast<const LT*>(a.lodf_sel);
+    {
+      typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
+      constexpr bool kF64 = std::is_same<R, double>::value;
+      const DevProblem& p = a.p;
+      const DevWork& w = a.w;
+      const int lane = threadIdx.x & 63;
+      const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      const int T = p.T, Lp = p.Lp, Kp = p.Kp;
+      const int tw = (bz * WL + wv) * TCW;  // first period of the wavefront
+      const int ntw = min(TCW, T - tw);
+      if (ntw > 0) {
+      const int k = kb * 64 + lane;  // slot of the lane
+      const int kc = a.act_k ? a.act_k[k] : k;
+      // z and S of the wavefront's (period, lane) pairs live in its own slice
+      // of LDS: only the per-branch path and the final store touch them
+      double* zsh = dyn + (size_t)wv * TCW * 128;
+      double* ssh = zsh + TCW * 64;
+      R fk[TCW];
+    #pragma unroll
+      for (int i = 0; i < TCW; ++i) {
+        fk[i] = i < ntw ? (R)w.Fk[(size_t)(tw + i) * Kp + kc] : R(0);
+        zsh[i * 64 + lane] = 0.0;
+        ssh[i * 64 + lane] = 0.0;
+      }
+      const cdouble* Sc = as_const(p.ctg_smax2);
+      const cdouble* Mc = as_const(p.ctg_smax);
+      const cdouble* Dc = as_const(p.dt);
+      const cdouble* Qc = as_const(w.q2);
+      const cdouble* FH = as_const(w.fh);
+      const double beta = w.params[PB_BETA];
+      const R eps = (R)w.params[PB_EPS];
+      const R eps2 = eps * eps;
+      const int ei = lane >> 3, eg = lane & 7;
+      const int l0 = lb * a.lt * 8;
+      const int l1 = min(Lp, l0 + a.lt * 8);
+      // FP64: F and thr of the next (period, tile) to be tested, from the
+      // branch-tiled copy (one 128-byte row per tile and period, so that the
+      // period-ahead prefetch is a fixed offset from the tile's row of period tw)
+      double Fn[8], Hn[8];
+      if constexpr (kF64) {
+        const cdouble* r = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
+    #pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          Fn[g] = r[g];
+          Hn[g] = r[8 + g];
+        }
+      }
+      const uint32_t live = (1u << ntw) - 1u;  // the wave's periods among the TCW tested
+      for (int lbase = l0; lbase < l1; lbase += 8) {
+        const cdouble* cur = FH + ((size_t)(lbase >> 3) * T + tw) * 16;
+        const cdouble* nxt = cur + (size_t)T * 16;  // period tw of the next tile
+        R lod[8];
+    #pragma unroll
+        for (int j = 0; j < 8; ++j) lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
+        R fv = R(0), qv = R(0), smx2[8];
+        if constexpr (!kF64) {
+          if (ei < ntw) {
+            const size_t e = (size_t)(tw + ei) * Lp + lbase + eg;
+            fv = (R)w.F[e];
+            qv = (R)w.q2[e];
+          }
+    #pragma unroll
+          for (int j = 0; j < 8; ++j) smx2[j] = (R)Sc[lbase + j];
+        }
+        // The test of every (period, branch, lane) of the tile, without a
+        // branch: all TCW periods are tested (the rows past the wave's last
+        // period are spare rows of the array, and their verdicts are dropped
+        // with the mask), and each period's verdict is one bit of hotm.
+        uint32_t hotm = 0;
+    #pragma unroll
+        for (int i = 0; i < TCW; ++i) {
+          uint64_t hot = 0;
+          if constexpr (kF64) {
+            double Fr[8], Hr[8];
+    #pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              Fr[g] = Fn[g];
+              Hr[g] = Hn[g];
+            }
+            // prefetch: the next period of this tile, else period tw of the
+            // next tile (rows past the tile or the last tile are spare rows)
+            const cdouble* q = (i + 1 < TCW) ? cur + 16 * (i + 1) : nxt;
+    #pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              Fn[g] = q[g];
+              Hn[g] = q[8 + g];
+            }
+    #pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              const double P = fma_uniform_c(lod[g], fk[i], Fr[g]);
+              hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+            }
+          } else {
+    #pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              const R Fr = readlane_any(fv, i * 8 + g);
+              const R P = fma_uniform_c(lod[g], fk[i], Fr);
+              const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
+              hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+            }
+          }
+          hotm |= (hot != 0 ? 1u : 0u) << i;
+        }
+        hotm &= live;
+        // a wave with fewer than TCW periods prefetched a spare row for the
+        // next tile: load its first period's row again
+        if constexpr (kF64) {
+          if (ntw < TCW) {
+    #pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              Fn[g] = nxt[g];
+              Hn[g] = nxt[8 + g];
+            }
+          }
+        }
+        // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
+        R racc = R(0), qacc = R(0);
+        if (hotm) {
+          // the overloaded periods of the tile: the per-branch path, with F,
+          // qmax2 and the ratings loaded again
+    #pragma unroll
+          for (int i = 0; i < TCW; ++i) {
+            if ((hotm >> i) & 1u) {
+              const R kt = (R)(Dc[tw + i] * p.c_s * beta);
+              R Fr[8], Qr[8], Sr[8];
+    #pragma unroll
+              for (int g = 0; g < 8; ++g) {
+                if constexpr (kF64) {
+                  Fr[g] = cur[16 * i + g];
+                  Qr[g] = Qc[(size_t)(tw + i) * Lp + lbase + g];
+                  Sr[g] = Sc[lbase + g];
+                } else {
+                  Fr[g] = readlane_any(fv, i * 8 + g);
+                  Qr[g] = readlane_any(qv, i * 8 + g);
+                  Sr[g] = smx2[g];
+                }
+              }
+              R zt = R(0), st = R(0);
+    #pragma unroll
+              for (int g = 0; g < 8; ++g) {
+                // the flow formed again (the same fused operation, so the same
+                // value as in the test)
+                const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
+                const R s2 = fma(P, P, Qr[g]);
+                if (__builtin_amdgcn_ballot_w64(s2 > Sr[g])) {
+                  R dP = R(0), dq = R(0);
+                  if (s2 > Sr[g]) {
+                    zt += ctg_overload(P, s2, (R)Mc[lbase + g], eps, eps2, kt, dP, dq);
+                    st = fma(lod[g], dP, st);
+                  }
+                  const R r = pair_sum(dP, dq);  // lane 0: sum of dP, lane 32: of dq
+                  racc = writelane_set(racc, readlane_any(r, 0), i * 8 + g);
+                  qacc = writelane_set(qacc, readlane_any(r, 32), i * 8 + g);
+                }
+              }
+              zsh[i * 64 + lane] += (double)zt;
+              ssh[i * 64 + lane] += (double)st;
+            }
+          }
+        }
+        // per (period, 8 branches): stored only when not all zero, and flagged
+        const uint64_t b = hotm ? __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0)) : 0;
+        if (lane < ntw)
+          w.rflag[((size_t)(tw + lane) * (Lp / 8) + lbase / 8) * a.rfs + kb] =
+              (uint8_t)(((b >> (8 * lane)) & 0xFF) != 0);
+        if (b != 0 && lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
+          const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
+          w.rpart[o] = (double)racc;
+          w.qpart[o] = (double)qacc;
+        }
+      }
+    #pragma unroll
+      for (int i = 0; i < TCW; ++i) {
+        if (i < ntw) {
+          // stored only when not all zero, and flagged
+          const double z = zsh[i * 64 + lane], s2 = ssh[i * 64 + lane];
+          const bool nz = __builtin_amdgcn_ballot_w64(z != 0.0 || s2 != 0.0) != 0;
+          if (lane == 0) w.zflag[((size_t)(tw + i) * a.zfk + kb) * a.zfs + lb] = (uint8_t)nz;
+          if (nz) {
+            const size_t o = ((size_t)lb * T + tw + i) * Kp + k;
+            w.zpart[o] = z;
+            w.spart[o] = s2;
+          }
+        }
+      }
+      }
+
+    }
   }
 }
 

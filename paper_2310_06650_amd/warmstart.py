@@ -1,19 +1,28 @@
 """Learned warm start: a network that maps a day's loads to an initial point
 of the solver, trained on the solver's own solutions.
 
-    python -m paper_2310_06650_amd.warmstart [--train 256] [--test 16]
+    python -m paper_2310_06650_amd.warmstart [--train 2000] [--test 200]
 
-The paper starts Adam from a copper-plate dispatch and names machine
-learning as future work (Sections III and V).  Here the grid is fixed and the
-loads vary from day to day (synth.load_draw); for each training day the plain
-solve on the GPU (qg_solve from the flat start) produces a solution, and an
-MLP (qg_mlp.h; FP32 training, BF16 inference) learns loads -> solution.  On
-held-out days the network's prediction, clipped to the box, starts a shorter
-solve, and the time to come within 1 % of the plain solve's best score is
-compared with the plain solve's own time to get there.
+The paper starts Adam from the copper-plate dispatch (Section III) and names
+machine learning as future work (Section V).  Here the grid is fixed and the
+loads vary from day to day (synth.load_draw).  For each training day the
+plain solve produces a solution (same-grid days solved together through the
+batched step, qg_solve_batch); an MLP (qg_mlp.h; FP32 training, BF16
+inference) learns loads -> solution.
+
+On held-out days the network's prediction, clipped to the box, starts the
+solver, and is compared with three other starts under the same schedules and
+horizons, so that the network's own gain is measured apart from the
+schedule's: the flat start (v = 1, theta = 0, u = 1, proportional p), the
+copper-plate start (the LP dispatch p, q, r, u of the relaxation with
+v = 1, theta = 0) and the mean of the training solutions.  The yardstick of
+every run is the same: 0.99 x the score of the plain solve (flat start, plain
+schedule) after its full horizon, as a ratio to the copper-plate bound z_ed;
+a run stops at the first checked step that reaches it.
 
 Everything on the device runs through the library's kernels; this module
-marshals arrays, standardises features and targets, and schedules the work.
+marshals arrays, standardises features and targets, shuffles the training
+set on the host, and schedules the work.
 """
 from __future__ import annotations
 
@@ -27,13 +36,14 @@ import numpy as np
 
 from . import qg, synth
 
-# schedules (qg_solve_opts keywords): the plain solve from the flat start, and
-# the solve from a predicted point (penalties at full weight, a narrower
-# smoothing range and smaller steps, since it starts near a solution)
+# schedules (qg_solve_opts keywords): the plain solve's (long, starting with
+# soft penalties and wide smoothing) and a short one for starts near a
+# solution (penalties at full weight, narrower smoothing, smaller steps)
 PLAIN = dict(alpha0=3e-3, alphaf=1e-5, eps0=1e-1, epsf=1e-4, beta0=0.1, betaf=1.0, rho0=0.1,
              rhof=1.0)
 WARM = dict(alpha0=1e-3, alphaf=1e-5, eps0=1e-2, epsf=1e-4, beta0=1.0, betaf=1.0, rho0=1.0,
             rhof=1.0)
+STARTS = ("flat", "copper", "mean", "net")
 
 
 def features(case, draw):
@@ -52,6 +62,14 @@ def box(case):
                          np.tile(case.gen_pmax, T), np.tile(case.gen_qmax, T),
                          np.tile(case.gen_rmax, T), np.ones(T * G)])
     return lo, hi
+
+
+def opts_for(sched, n_steps, z_ed=0.0, stop_ratio=2.0, check_every=0, skip_final=0):
+    return qg.solve_opts(n_steps, [sched["alpha0"]] * 6, alphaf=[sched["alphaf"]] * 6,
+                         n_total=n_steps, eps0=sched["eps0"], epsf=sched["epsf"],
+                         beta0=sched["beta0"], betaf=sched["betaf"], rho0=sched["rho0"],
+                         rhof=sched["rhof"], z_ed=z_ed, stop_ratio=stop_ratio,
+                         check_every=check_every, use_graph=1, skip_final=skip_final)
 
 
 class Worker:
@@ -77,12 +95,8 @@ class Worker:
             self.x.copy_(torch.as_tensor(x0))
             self.m.zero_()
             self.v.zero_()
-        opts = qg.solve_opts(n_steps, [sched["alpha0"]] * 6, alphaf=[sched["alphaf"]] * 6,
-                             n_total=n_steps, eps0=sched["eps0"], epsf=sched["epsf"],
-                             beta0=sched["beta0"], betaf=sched["betaf"], rho0=sched["rho0"],
-                             rhof=sched["rhof"], z_ed=z_ed, stop_ratio=stop_ratio,
-                             check_every=check_every, use_graph=1)
-        rep = self.prob.solve(self.x, self.m, self.v, opts)
+        rep = self.prob.solve(self.x, self.m, self.v,
+                              opts_for(sched, n_steps, z_ed, stop_ratio, check_every))
         self.stream.synchronize()
         return rep
 
@@ -94,27 +108,49 @@ def flat_for(case, draw):
     return synth.flat_start(synth.with_loads(case, draw))
 
 
-def generate(case, seeds, n_steps, workers=4):
-    """(X, Y): features and plain-solve solutions of the given load draws."""
-    pool = [Worker(case) for _ in range(workers)]
+def copper_for(case, lp):
+    """The copper-plate start: the LP's p, q, r, u; v = 1 and theta = 0."""
+    T, N = case.n_period, case.n_bus
+    return np.concatenate([np.ones(T * N), np.zeros(T * N),
+                           np.asarray(lp.p).reshape(-1), np.asarray(lp.q).reshape(-1),
+                           np.asarray(lp.r).reshape(-1), np.asarray(lp.u).reshape(-1)])
+
+
+def generate(case, seeds, n_steps, batch=64, tile="s4x4x8", log=None):
+    """(X, Y): features and plain-solve solutions of the given load draws,
+    solved batch days at a time through the batched step (each problem of the
+    batch is the same grid with that day's loads)."""
+    import torch
+    nb = min(batch, len(seeds))
+    probs = [qg.Problem(case) for _ in range(nb)]
+    for p in probs:
+        if p.K > 0:
+            p.set_tile(tile)
+    xs = [p.new_vector() for p in probs]
+    ms = [p.new_vector() for p in probs]
+    vs = [p.new_vector() for p in probs]
     X = np.zeros((len(seeds), case.n_period * (case.n_bus + 1)))
     Y = np.zeros((len(seeds), case.n_x))
-
-    def job(i):
-        w = pool[i % workers]
-        draw = synth.load_draw(case, seeds[i])
-        w.solve(draw, flat_for(case, draw), n_steps, PLAIN)
-        X[i] = features(case, draw)
-        Y[i] = w.x.cpu().numpy()
-
-    # one thread per worker: jobs of a worker run in order on its stream
-    with cf.ThreadPoolExecutor(workers) as ex:
-        futs = [ex.submit(lambda k=k: [job(i) for i in range(k, len(seeds), workers)])
-                for k in range(workers)]
-        for f in futs:
-            f.result()
-    for w in pool:
-        w.close()
+    opts = opts_for(PLAIN, n_steps)
+    for b0 in range(0, len(seeds), nb):
+        idx = list(range(b0, min(b0 + nb, len(seeds))))
+        for p, x, m, v, i in zip(probs, xs, ms, vs, idx):
+            draw = synth.load_draw(case, seeds[i])
+            p.update_loads(*draw)
+            x.copy_(torch.as_tensor(flat_for(case, draw)))
+            m.zero_()
+            v.zero_()
+            X[i] = features(case, draw)
+        torch.cuda.synchronize()
+        k = len(idx)
+        qg.solve_batch(probs[:k], xs[:k], ms[:k], vs[:k], opts)
+        torch.cuda.synchronize()
+        for x, i in zip(xs, idx):
+            Y[i] = x.cpu().numpy()
+        if log:
+            log(f"training data: {idx[-1] + 1} of {len(seeds)} days")
+    for p in probs:
+        p.close()
     return X, Y
 
 
@@ -133,12 +169,13 @@ class Scaler:
 class WarmStart:
     """Standardisers and the trained network."""
 
-    def __init__(self, case, X, Y, width=512, depth=3, seed=0):
+    def __init__(self, case, X, Y, width=512, depth=3, seed=0, batch=64):
         import torch
         self.torch = torch
         self.case = case
+        self.batch = batch
         self.sx, self.sy = Scaler(X), Scaler(Y)
-        self.net = qg.MLP(X.shape[1], width, depth, Y.shape[1], max_batch=max(64, len(X)))
+        self.net = qg.MLP(X.shape[1], width, depth, Y.shape[1], max_batch=max(batch, 64))
         # He-style initialisation drawn on the host and uploaded
         rng = np.random.default_rng(seed)
         flat = np.zeros(self.net.n_params, dtype=np.float32)
@@ -147,108 +184,156 @@ class WarmStart:
             wo, _ = self.net.offsets(i)
             flat[wo:wo + a * b] = rng.normal(0.0, np.sqrt(2.0 / a), a * b).astype(np.float32)
         self.net.set_params(flat)
-        self.Xn = torch.as_tensor(self.sx.fwd(X), dtype=torch.float32).cuda()
-        self.Yn = torch.as_tensor(self.sy.fwd(Y), dtype=torch.float32).cuda()
+        self.Xn = self.sx.fwd(X).astype(np.float32)
+        self.Yn = self.sy.fwd(Y).astype(np.float32)
 
-    def train(self, steps, batch=64, lr=1e-3, seed=0):
+    def train(self, steps, lr=1e-3, seed=0):
+        """Adam on mini-batches of a per-epoch host shuffle: each epoch's
+        permuted copy of the standardised set is uploaded once and the
+        batches are contiguous slices of it."""
+        torch = self.torch
         rng = np.random.default_rng(seed)
         n = self.Xn.shape[0]
+        bs = min(self.batch, n)
+        # batches start at multiples of 64 rows of FP32, so on 256-byte
+        # boundaries as the network's entry points require
+        assert bs % 64 == 0 or bs == n, "batch must be a multiple of 64 rows"
+        per_epoch = n // bs
         losses = []
-        for it in range(steps):
-            idx = self.torch.as_tensor(rng.choice(n, size=min(batch, n), replace=False)).cuda()
-            xb = self.Xn.index_select(0, idx).contiguous()
-            yb = self.Yn.index_select(0, idx).contiguous()
-            loss = self.net.train_step(xb, yb, lr)
-            if it % 50 == 0 or it == steps - 1:
-                losses.append(float(loss))
+        it = 0
+        while it < steps:
+            perm = rng.permutation(n)
+            xe = torch.as_tensor(self.Xn[perm]).cuda()
+            ye = torch.as_tensor(self.Yn[perm]).cuda()
+            for q in range(per_epoch):
+                if it >= steps:
+                    break
+                loss = self.net.train_step(xe[q * bs:(q + 1) * bs], ye[q * bs:(q + 1) * bs], lr)
+                if it % 50 == 0 or it == steps - 1:
+                    losses.append(float(loss))
+                it += 1
         return losses
 
     def predict(self, draws, bf16=True):
         torch = self.torch
         X = np.stack([features(self.case, d) for d in draws])
-        xb = torch.as_tensor(self.sx.fwd(X), dtype=torch.float32).cuda()
-        if bf16:
-            self.net.to_bf16()
-            y = self.net.forward_bf16(xb)
-        else:
-            y = self.net.forward(xb)
-        torch.cuda.synchronize()
+        out = []
+        for b0 in range(0, len(X), self.batch):
+            xb = torch.as_tensor(self.sx.fwd(X[b0:b0 + self.batch]), dtype=torch.float32).cuda()
+            if bf16:
+                self.net.to_bf16()
+                y = self.net.forward_bf16(xb)
+            else:
+                y = self.net.forward(xb)
+            torch.cuda.synchronize()
+            out.append(y.cpu().numpy().astype(np.float64))
         lo, hi = box(self.case)
-        return np.clip(self.sy.inv(y.cpu().numpy().astype(np.float64)), lo, hi)
+        return np.clip(self.sy.inv(np.concatenate(out)), lo, hi)
 
 
-def compare(case, ws, seeds, n_plain=20000, n_warm=4000, check_every=250):
-    """Per held-out day: the plain solve's best ratio after n_plain steps, the
-    steps and seconds it takes to come within 1 % of it, and the same for
-    solves started from the network's prediction (BF16 inference) and, as an
-    ablation, from the mean of the training solutions."""
+def compare(case, ws, seeds, n_plain=20000, n_warm=4000, check_every=250, workers=4,
+            log=None):
+    """Per held-out day: z_ed and the copper-plate dispatch (host LP), the
+    plain solve's score after n_plain steps (its best), then, for every start
+    (flat, copper-plate, mean of the training solutions, network) and both
+    schedules (plain: n_plain steps; warm: n_warm steps), the steps and
+    seconds to come within 1 % of that best (-1: not reached)."""
     from . import ed
-    w = Worker(case)
-    rows = []
     preds = ws.predict([synth.load_draw(case, s) for s in seeds])
     lo, hi = box(case)
     x_mean = np.clip(ws.sy.mu, lo, hi)
-    for s, x_pred in zip(seeds, preds):
+    pool = [Worker(case) for _ in range(workers)]
+    rows = [None] * len(seeds)
+    done = [0]
+
+    def job(k, w):
+        s = seeds[k]
         draw = synth.load_draw(case, s)
-        z_ed = ed.copper_plate(synth.with_loads(case, draw)).z_ed
-        best = w.solve(draw, flat_for(case, draw), n_plain, PLAIN).final_score / z_ed
+        t0 = time.perf_counter()
+        lp = ed.copper_plate(synth.with_loads(case, draw))
+        lp_s = time.perf_counter() - t0
+        z_ed = lp.z_ed
+        starts = dict(flat=flat_for(case, draw), copper=np.clip(copper_for(case, lp), lo, hi),
+                      mean=x_mean, net=preds[k])
+        best = w.solve(draw, starts["flat"], n_plain, PLAIN).final_score / z_ed
         target = 0.99 * best
-        row = dict(seed=int(s), best_ratio=best, target=target)
-        for name, x0, n, sched in (("plain", flat_for(case, draw), n_plain, PLAIN),
-                                   ("warm", x_pred, n_warm, WARM),
-                                   ("mean", x_mean, n_warm, WARM)):
-            r = w.solve(draw, x0, n, sched, z_ed=z_ed, stop_ratio=target,
-                        check_every=check_every)
-            row[name + "_steps"] = int(r.steps_to_gap)
-            row[name + "_s"] = r.time_to_gap_s
-            row[name + "_final_ratio"] = r.final_score / z_ed
-        rows.append(row)
-    w.close()
+        row = dict(seed=int(s), best_ratio=best, target=target, lp_s=lp_s)
+        for sname, sched, n in (("plain", PLAIN, n_plain), ("warm", WARM, n_warm)):
+            for start in STARTS:
+                r = w.solve(draw, starts[start], n, sched, z_ed=z_ed, stop_ratio=target,
+                            check_every=check_every)
+                row[f"{start}/{sname}/steps"] = int(r.steps_to_gap)
+                row[f"{start}/{sname}/s"] = float(r.time_to_gap_s)
+                row[f"{start}/{sname}/final"] = float(r.final_score / z_ed)
+        rows[k] = row
+
+    def lane(wi):
+        for k in range(wi, len(seeds), workers):
+            job(k, pool[wi])
+            done[0] += 1
+            if log and done[0] % 10 == 0:
+                log(f"held-out days compared: {done[0]} of {len(seeds)}")
+
+    with cf.ThreadPoolExecutor(workers) as ex:
+        for f in [ex.submit(lane, i) for i in range(workers)]:
+            f.result()
+    for w in pool:
+        w.close()
     return rows
+
+
+def summarise(rows):
+    """Per (start, schedule): days reaching the target, median steps and
+    seconds over the days that reach it, and median seconds over all days
+    with the schedule's full run time where it is not reached."""
+    out = {}
+    for sname in ("plain", "warm"):
+        for start in STARTS:
+            key = f"{start}/{sname}"
+            ok = [r for r in rows if r[key + "/steps"] > 0]
+            out[key] = dict(
+                reached=len(ok),
+                median_steps=float(np.median([r[key + "/steps"] for r in ok])) if ok else None,
+                median_s=float(np.median([r[key + "/s"] for r in ok])) if ok else None)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--train", type=int, default=256)
-    ap.add_argument("--test", type=int, default=16)
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--solve-steps", type=int, default=8000)
-    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--width", type=int, default=512)
     ap.add_argument("--depth", type=int, default=3)
-    ap.add_argument("--warm-steps", default="4000,8000",
-                    help="schedule lengths of the warm solves (comma list)")
+    ap.add_argument("--plain-steps", type=int, default=20000)
+    ap.add_argument("--warm-steps", type=int, default=4000)
     args = ap.parse_args()
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     case = synth.config_case(args.config)
     t0 = time.perf_counter()
-    X, Y = generate(case, list(range(10000, 10000 + args.train)), args.solve_steps)
+    X, Y = generate(case, list(range(10000, 10000 + args.train)), args.solve_steps, log=log)
     t1 = time.perf_counter()
-    print(f"training data: {args.train} days in {t1 - t0:.1f} s", file=sys.stderr, flush=True)
+    log(f"training data: {args.train} days in {t1 - t0:.1f} s")
     ws = WarmStart(case, X, Y, width=args.width, depth=args.depth)
     losses = ws.train(args.train_steps)
     t2 = time.perf_counter()
-    print(f"trained in {t2 - t1:.1f} s", file=sys.stderr, flush=True)
-    runs = {}
-    for n_warm in [int(v) for v in args.warm_steps.split(",")]:
-        runs[n_warm] = compare(case, ws, list(range(20000, 20000 + args.test)), n_warm=n_warm)
-        print(f"compared with {n_warm}-step warm schedules", file=sys.stderr, flush=True)
+    log(f"trained in {t2 - t1:.1f} s")
+    rows = compare(case, ws, list(range(20000, 20000 + args.test)), n_plain=args.plain_steps,
+                   n_warm=args.warm_steps, log=log)
     t3 = time.perf_counter()
-    def med(rows, key):
-        v = [r[key] for r in rows if r[key.split("_")[0] + "_steps"] > 0]
-        return float(np.median(v)) if v else None
-
     summary = dict(
         config=args.config, train_days=args.train, test_days=args.test,
         solve_steps=args.solve_steps, net=f"{X.shape[1]}-{args.width}x{args.depth}-{Y.shape[1]}",
         n_params=ws.net.n_params, data_s=t1 - t0, train_s=t2 - t1, eval_s=t3 - t2,
-        loss_first=losses[0], loss_last=losses[-1],
-        by_warm_schedule={
-            n: dict(reached={k: sum(r[k + "_steps"] > 0 for r in rows)
-                             for k in ("plain", "warm", "mean")},
-                    median_s={k: med(rows, k + "_s") for k in ("plain", "warm", "mean")},
-                    median_steps={k: med(rows, k + "_steps") for k in ("plain", "warm", "mean")})
-            for n, rows in runs.items()},
-        rows={n: rows for n, rows in runs.items()})
+        train_steps=args.train_steps, loss_first=losses[0], loss_last=losses[-1],
+        schedules=dict(plain=dict(PLAIN, steps=args.plain_steps),
+                       warm=dict(WARM, steps=args.warm_steps)),
+        by_start=summarise(rows), rows=rows)
     print(json.dumps(summary), flush=True)
 
 

@@ -1,7 +1,13 @@
-"""The learned warm start against the plain solve on held-out load days of
-the 617-bus grid: a small network trained on about a hundred of the solver's own
-solutions must reach the plain solve's 1 % target in fewer steps than the
-plain solve needs from the flat start."""
+"""What the trained network adds (Section III's copper-plate start, Section
+V's learning as future work), on held-out load days of the 617-bus grid: a
+network trained on 512 of the solver's own solutions, and every other start
+(flat, copper-plate LP dispatch, mean of the training solutions) run under
+the same schedules and horizons, score checked every 50 steps.  Under the
+short warm schedule the network's start must reach the plain solve's 1 %
+target on at least three of four days, on each of them sooner than the flat
+and copper-plate starts (which need the long schedule) and sooner than the
+plain solve, and summed over the days no later than the mean of the
+solutions (a start that misses counts the whole horizon)."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -16,15 +22,28 @@ def ws_mod():
     return warmstart
 
 
-def test_learned_start_reaches_the_target_sooner(ws_mod):
+def test_learned_start_gains_over_every_other_start(ws_mod):
     from paper_2310_06650_amd import synth
     case = synth.config_case("c2")
-    X, Y = ws_mod.generate(case, list(range(10000, 10096)), 8000)
+    X, Y = ws_mod.generate(case, list(range(10000, 10512)), 8000)
     ws = ws_mod.WarmStart(case, X, Y, width=512, depth=3)
-    losses = ws.train(800)
-    assert losses[-1] < 0.1 * losses[0]
-    rows = ws_mod.compare(case, ws, [20000, 20001], n_warm=8000)
+    losses = ws.train(1500)
+    assert losses[-1] < 0.3 * losses[0]
+    n_warm = 4000
+    rows = ws_mod.compare(case, ws, [20000, 20001, 20002, 20003], n_warm=n_warm,
+                          check_every=50, workers=2)
+
+    def steps(r, key):  # a start that misses the target counts the whole horizon
+        s = r[key + "/steps"]
+        return s if s > 0 else n_warm + 1
+
+    reached = [r for r in rows if r["net/warm/steps"] > 0]
     for r in rows:
-        print(r)
-        assert r["plain_steps"] > 0 and r["warm_steps"] > 0
-        assert r["warm_steps"] < r["plain_steps"]
+        print({k: v for k, v in r.items() if k.endswith("/steps")})
+    assert len(reached) >= 3
+    for r in reached:
+        assert r["net/warm/steps"] < r["flat/plain/steps"]
+        assert r["net/warm/s"] < r["flat/plain/s"]
+        assert r["net/warm/steps"] < steps(r, "flat/warm")
+        assert r["net/warm/steps"] < steps(r, "copper/warm")
+    assert sum(steps(r, "net/warm") for r in rows) <= sum(steps(r, "mean/warm") for r in rows)
