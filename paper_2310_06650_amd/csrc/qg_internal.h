@@ -84,9 +84,10 @@ struct DevWork {
   int64_t* step;       // [1] index of the current step in the schedule table
   double* sched;       // [kSchedCap][kSchedStride] per-step eps, beta, rho_s, alpha[6], bc1, bc2
   double* snext;       // [kSchedStride] the schedule row of the next scheduled evaluation
-  double* fh;          // [Lp/8 + 1][T][16] (+ 8 rows): per 8-branch tile and period, F of
-                       // the 8 branches then their test radii thr (the same values as F,
-                       // thr); the spare tile and rows absorb the map-reduce's prefetch
+  double* fh;          // [Lp/8 + 1][T][16] (+ 8 rows): per 8-branch tile and period, F and
+                       // the test radii thr of branches 0-3, then of branches 4-7 (the
+                       // same values as F, thr); the spare tile and rows absorb the
+                       // map-reduce's prefetch
   double* epP; double* epQ;      // [T][2L] branch flows at bus-sorted endpoint slots
   double* bco;         // [9][T][L] per-branch reverse coefficients
   double* q2;          // [T][Lp]  max(q_fr^2, q_to^2)

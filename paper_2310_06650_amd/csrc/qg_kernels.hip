@@ -162,6 +162,15 @@ __device__ __forceinline__ double swap_add(double a, double b) {
   return __hiloint2double((int)xhi, (int)xlo) + __hiloint2double((int)yhi, (int)ylo);
 }
 
+// dpp_f64 for patterns that read a lane of the same row for every lane
+// (quad permutations, mirrors): no lane keeps its old value, so none is set.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_row(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Wavefront totals of two per-lane values at once (all lanes active): lanes
 // 0..31 return the sum of a over the 64 lanes, lanes 32..63 the sum of b.
 // The 32-lane swap leaves a's pair sums in the low half and b's in the high
@@ -170,10 +179,10 @@ __device__ __forceinline__ double swap_add(double a, double b) {
 __device__ __forceinline__ double pair_sum(double a, double b) {
   double v = swap_add<32>(a, b);
   v = swap_add<16>(v, v);
-  v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror
-  v += dpp_f64<0x140, 0xF>(v);   // row_mirror
+  v += dpp_f64_row<0xB1>(v);     // quad_perm [1,0,3,2]
+  v += dpp_f64_row<0x4E>(v);     // quad_perm [2,3,0,1]
+  v += dpp_f64_row<0x141>(v);    // row_half_mirror
+  v += dpp_f64_row<0x140>(v);    // row_mirror
   return v;
 }
 
@@ -197,6 +206,12 @@ __device__ __forceinline__ float fma_uniform_c(float a, float b, float c) {
   asm("v_fma_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
   return d;
 }
+
+// Branch-tiled copy of F and thr (w.fh): per 8-branch tile and period one
+// 128-byte row of two 64-byte halves, [F0..F3 thr0..thr3][F4..F7 thr4..thr7],
+// so that one 16-dword scalar load brings the F and thr of four branches.
+__device__ __forceinline__ constexpr int fh_col_f(int g) { return (g >> 2) * 8 + (g & 3); }
+__device__ __forceinline__ constexpr int fh_col_h(int g) { return (g >> 2) * 8 + 4 + (g & 3); }
 
 // ---- FP32 counterparts for the reduced-precision contingency map-reduce
 
@@ -252,6 +267,27 @@ __device__ __forceinline__ float pair_sum(float a, float b) {
   v += dpp_f32<0x141>(v);
   v += dpp_f32<0x140>(v);
   return v;
+}
+
+// Raw buffer resource over `bytes` bytes from `base` (gfx9 word 3): the
+// address of a buffer access is base + the lane's 32-bit offset (VGPR) + a
+// wavefront-uniform offset (SGPR), so a loop that advances the uniform offset
+// needs no per-lane address arithmetic.  Loads past the end return 0 and
+// stores past it are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double lodf_buf(__amdgpu_buffer_rsrc_t r, const double*, unsigned v,
+                                           unsigned s) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+}
+__device__ __forceinline__ float lodf_buf(__amdgpu_buffer_rsrc_t r, const float*, unsigned v,
+                                          unsigned s) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+__device__ __forceinline__ float lodf_buf(__amdgpu_buffer_rsrc_t r, const uint16_t*, unsigned v,
+                                          unsigned s) {
+  return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0) << 16);
 }
 
 // Outage factor of the stored kind, widened to the arithmetic type.
@@ -577,7 +613,7 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
     const double A = p.ctg_smax2[l] * (1.0 - 0x1p-40) - qm2;
     const double thr = A > 0.0 ? sqrt(A) * (1.0 - 0x1p-50) : -1.0;
     w.thr[(size_t)t * p.Lp + l] = thr;
-    w.fh[((size_t)(l >> 3) * T + t) * 16 + 8 + (l & 7)] = thr;
+    w.fh[((size_t)(l >> 3) * T + t) * 16 + fh_col_h(l & 7)] = thr;
     const size_t TL = (size_t)T * L, e = (size_t)t * L + l;
     w.bco[0 * TL + e] = cs;
     w.bco[1 * TL + e] = sn;
@@ -719,7 +755,7 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
   for (int l = p.L + tid; l < p.Lp; l += kBlock) {
     w.q2[(size_t)t * p.Lp + l] = 0.0;
     w.thr[(size_t)t * p.Lp + l] = -1.0;
-    w.fh[((size_t)(l >> 3) * p.T + t) * 16 + 8 + (l & 7)] = -1.0;
+    w.fh[((size_t)(l >> 3) * p.T + t) * 16 + fh_col_h(l & 7)] = -1.0;
   }
   for (int k = p.K + tid; k < p.Kp; k += kBlock) w.Fk[(size_t)t * p.Kp + k] = 0.0;
 }
@@ -758,7 +794,7 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
     if (t < T) {
       const double f = v - cload[(size_t)t * Lp + col];
       F[(size_t)t * Lp + col] = f;
-      FH[((size_t)(col >> 3) * T + t) * 16 + (col & 7)] = f;
+      FH[((size_t)(col >> 3) * T + t) * 16 + fh_col_f(col & 7)] = f;
       const int k = kof[col];
       if (k >= 0) Fk[(size_t)t * Kp + k] = f;
     }
@@ -1088,25 +1124,44 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
   const int ei = lane >> 3, eg = lane & 7;
   const int l0 = lb * a.lt * 8;
   const int l1 = min(Lp, l0 + a.lt * 8);
-  // FP64: F and thr of the next (period, tile) to be tested, from the
-  // branch-tiled copy (one 128-byte row per tile and period, so that the
-  // period-ahead prefetch is a fixed offset from the tile's row of period tw)
-  double Fn[8], Hn[8];
+  // The factor loads of the tile loop go through a buffer resource over
+  // the block's rows: the lane's fixed 32-bit byte offset (its slot k) plus
+  // a uniform row offset that advances with the tile, so the loop needs no
+  // per-lane address arithmetic.
+  unsigned rowb = (unsigned)a.kst * (unsigned)sizeof(LT);  // bytes per factor row
+  const __amdgpu_buffer_rsrc_t lrs =
+      buf_rsrc(lodf + (size_t)l0 * a.kst, (unsigned)(l1 - l0) * rowb);
+  const unsigned koff = (unsigned)k * (unsigned)sizeof(LT);
+  // R/Q flags of the lane's period (lane e < ntw: period tw + e), bit i for
+  // tile i of the block, stored after the loop
+  uint64_t fbits = 0;
+  // FP64: F and thr of the next half row (four branches of one period) to be
+  // tested, from the branch-tiled copy, so that every prefetch is a fixed
+  // offset from the tile's row of period tw
+  double Fn[4], Hn[4];
   if constexpr (kF64) {
     const cdouble* r = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
+    for (int g = 0; g < 4; ++g) {
       Fn[g] = r[g];
-      Hn[g] = r[8 + g];
+      Hn[g] = r[4 + g];
     }
   }
   const uint32_t live = (1u << ntw) - 1u;  // the wave's periods among the TCW tested
-  for (int lbase = l0; lbase < l1; lbase += 8) {
-    const cdouble* cur = FH + ((size_t)(lbase >> 3) * T + tw) * 16;
-    const cdouble* nxt = cur + (size_t)T * 16;  // period tw of the next tile
+  unsigned lso = 0;  // uniform offset of the tile's factor rows
+  int ti = 0;        // tile index in the block
+  // rows of the branch-tiled copy: period tw of the tile, of the next tile
+  const cdouble* cur = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
+  unsigned fstep = (unsigned)T * 16u;
+  for (int lbase = l0; lbase < l1; lbase += 8, lso += 8 * rowb, ++ti, cur += fstep) {
+    // the strides are taken as changing in every tile, so that nothing
+    // derived from them is hoisted out of the loop (such values took SGPRs
+    // that were then spilled, and reloading them costs vector instructions)
+    asm volatile("" : "+s"(rowb), "+s"(fstep));
+    const cdouble* nxt = cur + fstep;
     R lod[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
+    for (int j = 0; j < 8; ++j) lod[j] = lodf_buf(lrs, lodf, koff, lso + j * rowb);
     R fv = R(0), qv = R(0), smx2[8];
     if constexpr (!kF64) {
       if (ei < ntw) {
@@ -1126,24 +1181,28 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
     for (int i = 0; i < TCW; ++i) {
       uint64_t hot = 0;
       if constexpr (kF64) {
-        double Fr[8], Hr[8];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          Fr[g] = Fn[g];
-          Hr[g] = Hn[g];
-        }
-        // prefetch: the next period of this tile, else period tw of the
-        // next tile (rows past the tile or the last tile are spare rows)
-        const cdouble* q = (i + 1 < TCW) ? cur + 16 * (i + 1) : nxt;
+        for (int h = 0; h < 2; ++h) {
+          double Fr[4], Hr[4];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          Fn[g] = q[g];
-          Hn[g] = q[8 + g];
-        }
+          for (int g = 0; g < 4; ++g) {
+            Fr[g] = Fn[g];
+            Hr[g] = Hn[g];
+          }
+          // prefetch: the other half of this period's row, else the next
+          // period of this tile, else period tw of the next tile (rows past
+          // the tile or the last tile are spare rows)
+          const cdouble* q = h == 0 ? cur + 16 * i + 8 : (i + 1 < TCW) ? cur + 16 * (i + 1) : nxt;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          const double P = fma_uniform_c(lod[g], fk[i], Fr[g]);
-          hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+          for (int g = 0; g < 4; ++g) {
+            Fn[g] = q[g];
+            Hn[g] = q[4 + g];
+          }
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const double P = fma_uniform_c(lod[4 * h + g], fk[i], Fr[g]);
+            hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+          }
         }
       } else {
 #pragma unroll
@@ -1162,15 +1221,15 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
     if constexpr (kF64) {
       if (ntw < TCW) {
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
+        for (int g = 0; g < 4; ++g) {
           Fn[g] = nxt[g];
-          Hn[g] = nxt[8 + g];
+          Hn[g] = nxt[4 + g];
         }
       }
     }
-    // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
-    R racc = R(0), qacc = R(0);
     if (hotm) {
+      // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
+      R racc = R(0), qacc = R(0);
       // the overloaded periods of the tile: the per-branch path, with F,
       // qmax2 and the ratings loaded again
 #pragma unroll
@@ -1181,7 +1240,7 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
           for (int g = 0; g < 8; ++g) {
             if constexpr (kF64) {
-              Fr[g] = cur[16 * i + g];
+              Fr[g] = cur[16 * i + fh_col_f(g)];
               Qr[g] = Qc[(size_t)(tw + i) * Lp + lbase + g];
               Sr[g] = Sc[lbase + g];
             } else {
@@ -1196,7 +1255,7 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
             // the flow formed again (the same fused operation, so the same
             // value as in the test)
             const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
-            const R s2 = fma(P, P, Qr[g]);
+            const R s2 = fma_uniform_c(P, P, Qr[g]);
             if (__builtin_amdgcn_ballot_w64(s2 > Sr[g])) {
               R dP = R(0), dq = R(0);
               if (s2 > Sr[g]) {
@@ -1212,17 +1271,19 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
           ssh[i * 64 + lane] += (double)st;
         }
       }
+      // per (period, 8 branches): stored only when not all zero, and flagged
+      const uint64_t b = __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0));
+      if (lane < ntw && ((b >> (8 * lane)) & 0xFF) != 0) fbits |= (uint64_t)1 << ti;
+      if (b != 0 && lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
+        const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
+        w.rpart[o] = (double)racc;
+        w.qpart[o] = (double)qacc;
+      }
     }
-    // per (period, 8 branches): stored only when not all zero, and flagged
-    const uint64_t b = hotm ? __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0)) : 0;
-    if (lane < ntw)
-      w.rflag[((size_t)(tw + lane) * (Lp / 8) + lbase / 8) * a.rfs + kb] =
-          (uint8_t)(((b >> (8 * lane)) & 0xFF) != 0);
-    if (b != 0 && lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
-      const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
-      w.rpart[o] = (double)racc;
-      w.qpart[o] = (double)qacc;
-    }
+  }
+  if (lane < ntw) {
+    uint8_t* f = w.rflag + ((size_t)(tw + lane) * (Lp / 8) + (l0 >> 3)) * a.rfs + kb;
+    for (int i = 0; i < ti; ++i) f[(size_t)i * a.rfs] = (uint8_t)((fbits >> i) & 1u);
   }
 #pragma unroll
   for (int i = 0; i < TCW; ++i) {
@@ -1995,25 +2056,44 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
       const int ei = lane >> 3, eg = lane & 7;
       const int l0 = lb * a.lt * 8;
       const int l1 = min(Lp, l0 + a.lt * 8);
-      // FP64: F and thr of the next (period, tile) to be tested, from the
-      // branch-tiled copy (one 128-byte row per tile and period, so that the
-      // period-ahead prefetch is a fixed offset from the tile's row of period tw)
-      double Fn[8], Hn[8];
+      // The factor loads of the tile loop go through a buffer resource over
+      // the block's rows: the lane's fixed 32-bit byte offset (its slot k) plus
+      // a uniform row offset that advances with the tile, so the loop needs no
+      // per-lane address arithmetic.
+      unsigned rowb = (unsigned)a.kst * (unsigned)sizeof(LT);  // bytes per factor row
+      const __amdgpu_buffer_rsrc_t lrs =
+          buf_rsrc(lodf + (size_t)l0 * a.kst, (unsigned)(l1 - l0) * rowb);
+      const unsigned koff = (unsigned)k * (unsigned)sizeof(LT);
+      // R/Q flags of the lane's period (lane e < ntw: period tw + e), bit i for
+      // tile i of the block, stored after the loop
+      uint64_t fbits = 0;
+      // FP64: F and thr of the next half row (four branches of one period) to be
+      // tested, from the branch-tiled copy, so that every prefetch is a fixed
+      // offset from the tile's row of period tw
+      double Fn[4], Hn[4];
       if constexpr (kF64) {
         const cdouble* r = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
     #pragma unroll
-        for (int g = 0; g < 8; ++g) {
+        for (int g = 0; g < 4; ++g) {
           Fn[g] = r[g];
-          Hn[g] = r[8 + g];
+          Hn[g] = r[4 + g];
         }
       }
       const uint32_t live = (1u << ntw) - 1u;  // the wave's periods among the TCW tested
-      for (int lbase = l0; lbase < l1; lbase += 8) {
-        const cdouble* cur = FH + ((size_t)(lbase >> 3) * T + tw) * 16;
-        const cdouble* nxt = cur + (size_t)T * 16;  // period tw of the next tile
+      unsigned lso = 0;  // uniform offset of the tile's factor rows
+      int ti = 0;        // tile index in the block
+      // rows of the branch-tiled copy: period tw of the tile, of the next tile
+      const cdouble* cur = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
+      unsigned fstep = (unsigned)T * 16u;
+      for (int lbase = l0; lbase < l1; lbase += 8, lso += 8 * rowb, ++ti, cur += fstep) {
+        // the strides are taken as changing in every tile, so that nothing
+        // derived from them is hoisted out of the loop (such values took SGPRs
+        // that were then spilled, and reloading them costs vector instructions)
+        asm volatile("" : "+s"(rowb), "+s"(fstep));
+        const cdouble* nxt = cur + fstep;
         R lod[8];
     #pragma unroll
-        for (int j = 0; j < 8; ++j) lod[j] = lodf_load(lodf, (size_t)(lbase + j) * a.kst + k);
+        for (int j = 0; j < 8; ++j) lod[j] = lodf_buf(lrs, lodf, koff, lso + j * rowb);
         R fv = R(0), qv = R(0), smx2[8];
         if constexpr (!kF64) {
           if (ei < ntw) {
@@ -2033,24 +2113,28 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
         for (int i = 0; i < TCW; ++i) {
           uint64_t hot = 0;
           if constexpr (kF64) {
-            double Fr[8], Hr[8];
     #pragma unroll
-            for (int g = 0; g < 8; ++g) {
-              Fr[g] = Fn[g];
-              Hr[g] = Hn[g];
-            }
-            // prefetch: the next period of this tile, else period tw of the
-            // next tile (rows past the tile or the last tile are spare rows)
-            const cdouble* q = (i + 1 < TCW) ? cur + 16 * (i + 1) : nxt;
+            for (int h = 0; h < 2; ++h) {
+              double Fr[4], Hr[4];
     #pragma unroll
-            for (int g = 0; g < 8; ++g) {
-              Fn[g] = q[g];
-              Hn[g] = q[8 + g];
-            }
+              for (int g = 0; g < 4; ++g) {
+                Fr[g] = Fn[g];
+                Hr[g] = Hn[g];
+              }
+              // prefetch: the other half of this period's row, else the next
+              // period of this tile, else period tw of the next tile (rows past
+              // the tile or the last tile are spare rows)
+              const cdouble* q = h == 0 ? cur + 16 * i + 8 : (i + 1 < TCW) ? cur + 16 * (i + 1) : nxt;
     #pragma unroll
-            for (int g = 0; g < 8; ++g) {
-              const double P = fma_uniform_c(lod[g], fk[i], Fr[g]);
-              hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+              for (int g = 0; g < 4; ++g) {
+                Fn[g] = q[g];
+                Hn[g] = q[4 + g];
+              }
+    #pragma unroll
+              for (int g = 0; g < 4; ++g) {
+                const double P = fma_uniform_c(lod[4 * h + g], fk[i], Fr[g]);
+                hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+              }
             }
           } else {
     #pragma unroll
@@ -2069,15 +2153,15 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
         if constexpr (kF64) {
           if (ntw < TCW) {
     #pragma unroll
-            for (int g = 0; g < 8; ++g) {
+            for (int g = 0; g < 4; ++g) {
               Fn[g] = nxt[g];
-              Hn[g] = nxt[8 + g];
+              Hn[g] = nxt[4 + g];
             }
           }
         }
-        // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
-        R racc = R(0), qacc = R(0);
         if (hotm) {
+          // R and Q of (period tw + e / 8, branch lbase + e % 8) gather in lane e
+          R racc = R(0), qacc = R(0);
           // the overloaded periods of the tile: the per-branch path, with F,
           // qmax2 and the ratings loaded again
     #pragma unroll
@@ -2088,7 +2172,7 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
     #pragma unroll
               for (int g = 0; g < 8; ++g) {
                 if constexpr (kF64) {
-                  Fr[g] = cur[16 * i + g];
+                  Fr[g] = cur[16 * i + fh_col_f(g)];
                   Qr[g] = Qc[(size_t)(tw + i) * Lp + lbase + g];
                   Sr[g] = Sc[lbase + g];
                 } else {
@@ -2103,7 +2187,7 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
                 // the flow formed again (the same fused operation, so the same
                 // value as in the test)
                 const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
-                const R s2 = fma(P, P, Qr[g]);
+                const R s2 = fma_uniform_c(P, P, Qr[g]);
                 if (__builtin_amdgcn_ballot_w64(s2 > Sr[g])) {
                   R dP = R(0), dq = R(0);
                   if (s2 > Sr[g]) {
@@ -2119,17 +2203,19 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
               ssh[i * 64 + lane] += (double)st;
             }
           }
+          // per (period, 8 branches): stored only when not all zero, and flagged
+          const uint64_t b = __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0));
+          if (lane < ntw && ((b >> (8 * lane)) & 0xFF) != 0) fbits |= (uint64_t)1 << ti;
+          if (b != 0 && lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
+            const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
+            w.rpart[o] = (double)racc;
+            w.qpart[o] = (double)qacc;
+          }
         }
-        // per (period, 8 branches): stored only when not all zero, and flagged
-        const uint64_t b = hotm ? __builtin_amdgcn_ballot_w64(racc != R(0) || qacc != R(0)) : 0;
-        if (lane < ntw)
-          w.rflag[((size_t)(tw + lane) * (Lp / 8) + lbase / 8) * a.rfs + kb] =
-              (uint8_t)(((b >> (8 * lane)) & 0xFF) != 0);
-        if (b != 0 && lane < ntw * 8 && ((b >> (lane & ~7)) & 0xFF) != 0) {
-          const size_t o = ((size_t)kb * T + tw + ei) * Lp + lbase + eg;
-          w.rpart[o] = (double)racc;
-          w.qpart[o] = (double)qacc;
-        }
+      }
+      if (lane < ntw) {
+        uint8_t* f = w.rflag + ((size_t)(tw + lane) * (Lp / 8) + (l0 >> 3)) * a.rfs + kb;
+        for (int i = 0; i < ti; ++i) f[(size_t)i * a.rfs] = (uint8_t)((fbits >> i) & 1u);
       }
     #pragma unroll
       for (int i = 0; i < TCW; ++i) {
