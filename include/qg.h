@@ -93,6 +93,14 @@ enum { QG_CTG_ALL_NONBRIDGE = 0, QG_CTG_LIST = 1 };
  * accumulates them); the sum goes into the QG_T_CTG_MEAN slot and
  * QG_T_CTG_MAX is 0. */
 #define QG_FLAG_CTG_SUM 0x8u
+/* Bound-based skip of the FP64 contingency map-reduce.  Default: with FP64
+ * outage factors, every contingency scored and blocks of 4 to 32 / (periods
+ * per wavefront) branch tiles, a half row (4 branches, one period, 64
+ * contingencies) is passed over when |F_tl| + max|LODF_lk| max|F_tk| proves
+ * every post-outage flow within its test radius (with margins that cover the
+ * rounding), so the results are bitwise those of testing every element.
+ * With this flag every element is tested (a reference for that claim). */
+#define QG_FLAG_CTG_NO_SKIP 0x10u
 
 /* Grid description: host arrays, all FP64 per unit (100 MVA base) unless
  * stated; prices in $ per pu-hour, durations in hours. */

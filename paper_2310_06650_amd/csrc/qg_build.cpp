@@ -91,7 +91,7 @@ bool find_bridges(int N, int L, const int32_t* fr, const int32_t* to,
 
 // Byte layout of the constant arena.  The same walk gives the size (for
 // qg_problem_sizes) and the offsets (for the image).
-constexpr int kNConst = 46;
+constexpr int kNConst = 47;
 
 // FP32 -> BF16 with round to nearest even; NaN stays a (quiet) NaN.
 uint16_t to_bf16(float f) {
@@ -127,7 +127,8 @@ ConstLayout const_layout(const Problem& p) {
       (size_t)p.Lp * p.G16 * D,                   // isf_ga
       (size_t)p.Lp * p.Kp * lodf_elem_bytes(lodf_kind_of(p.flags)),  // lodf (FP64/FP32/BF16)
       T * (size_t)p.Lp * D,                       // cload
-      (size_t)p.Lp * D};                          // rsum
+      (size_t)p.Lp * D,                           // rsum
+      (size_t)(p.Lp / 4) * (p.Kp / 64) * D};      // lmaxh
   ConstLayout c;
   size_t o = 0;
   for (int i = 0; i < kNConst; ++i) {
@@ -332,7 +333,7 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   if ((o->flags & QG_FLAG_CTG_FP32) && (o->flags & QG_FLAG_CTG_BF16))
     return fail(QG_ERR_ARG, "at most one contingency precision flag");
   if (o->flags & ~(uint32_t)(QG_FLAG_CHECK_FINITE | QG_FLAG_CTG_FP32 | QG_FLAG_CTG_BF16 |
-                             QG_FLAG_CTG_SUM))
+                             QG_FLAG_CTG_SUM | QG_FLAG_CTG_NO_SKIP))
     return fail(QG_ERR_ARG, "unknown build flag");
   p->flags = o->flags;
   p->nb_br = (int)((int64_t(T) * L + kBlock - 1) / kBlock);
@@ -634,6 +635,23 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
         out[k] = (row[d->br_from[bk]] - row[d->br_to[bk]]) / denom[k];
       }
     });
+    // largest |factor| of every 4-branch group over every 64-contingency
+    // block (NaN entries left out): the bound of the map-reduce's skip test
+    {
+      double* lm = reinterpret_cast<double*>(img.data() + cl.off[46]);
+      const int nkb = Kp / 64;
+      parallel_for(Lp / 4, [&](int q) {
+        for (int kb = 0; kb < nkb; ++kb) {
+          double m = 0.0;
+          for (int l = 4 * q; l < 4 * q + 4; ++l)
+            for (int k = 64 * kb; k < 64 * kb + 64; ++k) {
+              const double v = std::fabs(lo[(size_t)l * Kp + k]);
+              if (v > m) m = v;  // false for NaN
+            }
+          lm[(size_t)q * nkb + kb] = m;
+        }
+      });
+    }
     if (kind == kLodfF32) {
       float* o32 = reinterpret_cast<float*>(img.data() + cl.off[43]);
       for (size_t e = 0; e < (size_t)Lp * Kp; ++e) o32[e] = (float)lo[e];
@@ -712,6 +730,7 @@ void rebase_pointers(Problem* p, void* arena) {
   dp.lodf_kind = lodf_kind_of(p->flags);
   dp.ctg_sum = (p->flags & QG_FLAG_CTG_SUM) ? 1 : 0;
   dp.lodf = dp.lodf_kind == kLodfF64 ? D(43) : nullptr;
+  dp.lmaxh = dp.lodf_kind == kLodfF64 && !(p->flags & QG_FLAG_CTG_NO_SKIP) ? D(46) : nullptr;
   dp.lodf32 = dp.lodf_kind == kLodfF32 ? reinterpret_cast<const float*>(base + cl.off[43]) : nullptr;
   dp.lodf16 =
       dp.lodf_kind == kLodfBF16 ? reinterpret_cast<const uint16_t*>(base + cl.off[43]) : nullptr;

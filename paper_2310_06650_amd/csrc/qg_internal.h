@@ -73,6 +73,8 @@ struct DevProblem {
   const float* lodf32;   //           the same in FP32 (QG_FLAG_CTG_FP32)
   const uint16_t* lodf16;  //         the same in BF16 (QG_FLAG_CTG_BF16)
   int lodf_kind;         // 0 FP64, 1 FP32, 2 BF16 (one of the three pointers is set)
+  const double* lmaxh;   // [Lp/4][Kp/64] max |lodf| of each 4-branch group and 64-contingency
+                         // block, NaN left out (FP64 factors only, else null)
   int ctg_sum;           // 1: per-period sum over contingencies instead of max + mean
   // prices
   double c_p, c_q, c_s, c_ang, ang_max, c_rsv, rho, vload;
@@ -295,6 +297,7 @@ struct BatchPlan {
   size_t bytes = 0;            // size of the batch buffer
   int lodf_kind = 0;
   int pm_grid = 0;             // blocks of the persistent map-reduce
+  bool skip = false;           // the map-reduce takes the skip test (FP64 factors)
 };
 constexpr int kBatchLocBits = 22;                  // block index bits of a table entry
 constexpr int kBatchWl = 4;                        // wavefronts per map-reduce block

@@ -186,6 +186,24 @@ __device__ __forceinline__ double pair_sum(double a, double b) {
   return v;
 }
 
+// Largest value over the 64 lanes of a wavefront (all lanes active), in every
+// lane: butterflies inside each row of 16 lanes, then the two cross-row
+// exchanges.  NaN inputs are dropped (fmax).
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_f64_row<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64_row<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64_row<0x141>(v));  // row_half_mirror
+  v = fmax(v, dpp_f64_row<0x140>(v));  // row_mirror
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  v = fmax(__hiloint2double((int)h[0], (int)l[0]), __hiloint2double((int)h[1], (int)l[1]));
+  const unsigned lo2 = __double2loint(v), hi2 = __double2hiint(v);
+  l = __builtin_amdgcn_permlane32_swap(lo2, lo2, false, false);
+  h = __builtin_amdgcn_permlane32_swap(hi2, hi2, false, false);
+  return fmax(__hiloint2double((int)h[0], (int)l[0]), __hiloint2double((int)h[1], (int)l[1]));
+}
+
 // Read-only view of device memory in the constant address space: loads at
 // wavefront-uniform addresses through it become scalar loads into SGPRs.
 // Only for data that no kernel of the same launch writes.
@@ -1060,6 +1078,52 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
   }
 }
 
+// Skip test of the period-split map-reduce (FP64 factors, every contingency
+// scored).  For a half row h (branches 4h..4h+3 of an 8-branch tile) of one
+// period, |P_tlk| = |F_tl + LODF_lk F_tk| <= |F_tl| + Lm Fm, where Lm is the
+// largest |LODF| of the 4 branches over the wave's 64 contingencies (a
+// per-grid table) and Fm the largest |F_tk| of the wave's lanes and periods.
+// When |F_tl| (1 + 2^-40) + Lm Fm <= thr_tl (1 - 2^-40) holds in floating
+// point for each of the 4 branches, no element of the half row passes the
+// test |fl(P)| > thr_tl: the margins cover the rounding of the bound, of its
+// comparison and of fl(P) (a few units of 2^-53), so the half row is skipped.
+// NaN in F or thr makes the comparison false (the half row is tested).  Lane
+// e of the wavefront decides half row (period tw + i, tile t0 + j) with
+// j = e / (2 TCW), i = (e / 2) % TCW, h = e % 2; periods past the wave's last
+// are skipped (their verdicts are dropped anyway).  Returns the ballot.
+template <int TCW>
+__device__ __forceinline__ uint64_t ctg_cold_mask(const double* __restrict__ fh,
+                                                  const double* __restrict__ lmaxh, int T,
+                                                  int tw, int ntw, int tile0, int ntile, int kb,
+                                                  int nkb, double fkm) {
+  constexpr int CT = 32 / TCW;  // tiles per mask
+  const int e = threadIdx.x & 63;
+  const int j = e / (2 * TCW), i = (e >> 1) % TCW, h = e & 1;
+  bool cold = false;
+  if (j < CT && j < ntile) {
+    if (i >= ntw) {
+      cold = true;
+    } else {
+      const int tile = tile0 + j;
+      const double* r = fh + ((size_t)tile * T + tw + i) * 16 + 8 * h;
+      const double lm = lmaxh[(size_t)(2 * tile + h) * nkb + kb];
+      double f[4], t[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        f[g] = r[g];
+        t[g] = r[4 + g];
+      }
+      cold = true;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const double s = fabs(f[g]) * (1.0 + 0x1p-40) - t[g] * (1.0 - 0x1p-40);
+        cold = cold && fma(lm, fkm, s) <= 0.0;
+      }
+    }
+  }
+  return __builtin_amdgcn_ballot_w64(cold);
+}
+
 // Period-split form of the same map-reduce.  The wavefronts of a block share
 // one range of lt * 8 branches and split the periods: wavefront w owns the
 // periods [t0 + w TCW, t0 + (w + 1) TCW), so z_tk and S_tk of its lanes need
@@ -1085,10 +1149,11 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
 // inlined function, which made the compiler spill about three times as many
 // SGPRs and the map-reduce 1.5x slower.  Batched and single steps are checked
 // to agree bit for bit.
-template <int TCW, typename LT>
+template <int TCW, typename LT, bool SKIP>
 __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
   typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
   constexpr bool kF64 = std::is_same<R, double>::value;
+  static_assert(kF64 || !SKIP, "the skip test bounds FP64 factors");
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int lane = threadIdx.x & 63;
@@ -1135,11 +1200,30 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
   // R/Q flags of the lane's period (lane e < ntw: period tw + e), bit i for
   // tile i of the block, stored after the loop
   uint64_t fbits = 0;
-  // FP64: F and thr of the next half row (four branches of one period) to be
+  // SKIP: half rows proved free of overloads are skipped (ctg_cold_mask),
+  // with FP64 factors, every contingency scored and a block of at most
+  // 32 / TCW tiles (one mask covers them all; the host launches the SKIP
+  // form only then, and a block outside it tests everything); the F and
+  // thr of a tested half row are loaded when it is reached.  Otherwise they
+  // are prefetched one half row ahead.
+  // bit (ti TCW + i) 2 + h: half row h of period tw + i of tile ti skipped
+  uint64_t coldm = 0;
+  if constexpr (SKIP) {
+    constexpr int CT = 32 / TCW;  // tiles per mask
+    const int ntile = (l1 - l0) >> 3;
+    if (p.lmaxh != nullptr && a.act_k == nullptr && ntile <= CT) {
+      double fkm = 0.0;  // largest |F_tk| of the wave's lanes and periods
+#pragma unroll
+      for (int i = 0; i < TCW; ++i) fkm = fmax(fkm, fabs(fk[i]));
+      fkm = wave_max(fkm);
+      coldm = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6, fkm);
+    }
+  }
+  // F and thr of the next half row (four branches of one period) to be
   // tested, from the branch-tiled copy, so that every prefetch is a fixed
   // offset from the tile's row of period tw
   double Fn[4], Hn[4];
-  if constexpr (kF64) {
+  if constexpr (kF64 && !SKIP) {
     const cdouble* r = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -1159,9 +1243,14 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
     // that were then spilled, and reloading them costs vector instructions)
     asm volatile("" : "+s"(rowb), "+s"(fstep));
     const cdouble* nxt = cur + fstep;
+    // the tile's half rows that are tested (bit 2 i + h); a tile without
+    // any is passed over, and only the factor rows of tested halves are loaded
+    const uint32_t need = ~(uint32_t)(coldm >> (ti * TCW * 2)) & ((1u << (2 * TCW)) - 1u);
+    if (need == 0) continue;
     R lod[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) lod[j] = lodf_buf(lrs, lodf, koff, lso + j * rowb);
+    for (int j = 0; j < 8; ++j)
+      lod[j] = (need & (j < 4 ? 0x5555u : 0xAAAAu)) ? lodf_buf(lrs, lodf, koff, lso + j * rowb) : R(0);
     R fv = R(0), qv = R(0), smx2[8];
     if constexpr (!kF64) {
       if (ei < ntw) {
@@ -1180,7 +1269,25 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
     for (int i = 0; i < TCW; ++i) {
       uint64_t hot = 0;
-      if constexpr (kF64) {
+      if constexpr (SKIP) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if ((need >> (2 * i + h)) & 1u) {
+            double Fr[4], Hr[4];
+            const cdouble* q = cur + 16 * i + 8 * h;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              Fr[g] = q[g];
+              Hr[g] = q[4 + g];
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              const double P = fma_uniform_c(lod[4 * h + g], fk[i], Fr[g]);
+              hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+            }
+          }
+        }
+      } else if constexpr (kF64) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           double Fr[4], Hr[4];
@@ -1218,7 +1325,7 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
     hotm &= live;
     // a wave with fewer than TCW periods prefetched a spare row for the
     // next tile: load its first period's row again
-    if constexpr (kF64) {
+    if constexpr (kF64 && !SKIP) {
       if (ntw < TCW) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -1252,6 +1359,9 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
           R zt = R(0), st = R(0);
 #pragma unroll
           for (int g = 0; g < 8; ++g) {
+            // a skipped half row holds no overload (and its factors were
+            // not loaded)
+            if (((need >> (2 * i + (g >> 2))) & 1u) == 0) continue;
             // the flow formed again (the same fused operation, so the same
             // value as in the test)
             const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
@@ -1826,11 +1936,25 @@ void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArg
   }
 }
 
+// The map-reduce takes the skip test (ctg_cold_mask) with FP64 factors,
+// every contingency scored and blocks of 4 to 32 / TCW branch tiles: with
+// fewer tiles per block the mask's cost is not recovered.
+constexpr int kSkipMinTiles = 4;
+inline bool ctg_skip(const EvalArgs& a, int tcw) {
+  return a.p.lmaxh != nullptr && a.act_k == nullptr && a.lt >= kSkipMinTiles && a.lt <= 32 / tcw;
+}
+
 template <int TCW, typename LT>
 void launch_ctg_pm_t(dim3 grid, dim3 block, hipStream_t s, const EvalArgs& a, const LT* lodf) {
   // z and S of every (wavefront, period, lane)
   const size_t lds = (size_t)(block.x / 64) * TCW * 128 * sizeof(double);
-  hipLaunchKernelGGL((k_ctg_pm<TCW, LT>), grid, block, lds, s, a, lodf);
+  if constexpr (std::is_same<LT, double>::value) {
+    if (ctg_skip(a, TCW)) {
+      hipLaunchKernelGGL((k_ctg_pm<TCW, LT, true>), grid, block, lds, s, a, lodf);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_ctg_pm<TCW, LT, false>), grid, block, lds, s, a, lodf);
 }
 
 template <typename LT>
@@ -2001,7 +2125,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_b(const EvalArgs* __restrict
 // barriers of the loop).  Items are ordered by decreasing work, so the
 // last ones to be taken are short.  Tiles: 4 wavefronts of 4 periods (the
 // problem's tile), its branch tiles per block free.
-template <typename LT>
+template <typename LT, bool SKIP>
 __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __restrict__ args,
                                                             const uint32_t* __restrict__ items,
                                                             int nitems, int* ctr) {
@@ -2067,11 +2191,30 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
       // R/Q flags of the lane's period (lane e < ntw: period tw + e), bit i for
       // tile i of the block, stored after the loop
       uint64_t fbits = 0;
-      // FP64: F and thr of the next half row (four branches of one period) to be
+      // SKIP: half rows proved free of overloads are skipped (ctg_cold_mask),
+      // with FP64 factors, every contingency scored and a block of at most
+      // 32 / TCW tiles (one mask covers them all; the host launches the SKIP
+      // form only then, and a block outside it tests everything); the F and
+      // thr of a tested half row are loaded when it is reached.  Otherwise they
+      // are prefetched one half row ahead.
+      // bit (ti TCW + i) 2 + h: half row h of period tw + i of tile ti skipped
+      uint64_t coldm = 0;
+      if constexpr (SKIP) {
+        constexpr int CT = 32 / TCW;  // tiles per mask
+        const int ntile = (l1 - l0) >> 3;
+        if (p.lmaxh != nullptr && a.act_k == nullptr && ntile <= CT) {
+          double fkm = 0.0;  // largest |F_tk| of the wave's lanes and periods
+    #pragma unroll
+          for (int i = 0; i < TCW; ++i) fkm = fmax(fkm, fabs(fk[i]));
+          fkm = wave_max(fkm);
+          coldm = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6, fkm);
+        }
+      }
+      // F and thr of the next half row (four branches of one period) to be
       // tested, from the branch-tiled copy, so that every prefetch is a fixed
       // offset from the tile's row of period tw
       double Fn[4], Hn[4];
-      if constexpr (kF64) {
+      if constexpr (kF64 && !SKIP) {
         const cdouble* r = FH + ((size_t)(l0 >> 3) * T + tw) * 16;
     #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -2091,9 +2234,14 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
         // that were then spilled, and reloading them costs vector instructions)
         asm volatile("" : "+s"(rowb), "+s"(fstep));
         const cdouble* nxt = cur + fstep;
+        // the tile's half rows that are tested (bit 2 i + h); a tile without
+        // any is passed over, and only the factor rows of tested halves are loaded
+        const uint32_t need = ~(uint32_t)(coldm >> (ti * TCW * 2)) & ((1u << (2 * TCW)) - 1u);
+        if (need == 0) continue;
         R lod[8];
     #pragma unroll
-        for (int j = 0; j < 8; ++j) lod[j] = lodf_buf(lrs, lodf, koff, lso + j * rowb);
+        for (int j = 0; j < 8; ++j)
+          lod[j] = (need & (j < 4 ? 0x5555u : 0xAAAAu)) ? lodf_buf(lrs, lodf, koff, lso + j * rowb) : R(0);
         R fv = R(0), qv = R(0), smx2[8];
         if constexpr (!kF64) {
           if (ei < ntw) {
@@ -2112,7 +2260,25 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
     #pragma unroll
         for (int i = 0; i < TCW; ++i) {
           uint64_t hot = 0;
-          if constexpr (kF64) {
+          if constexpr (SKIP) {
+    #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              if ((need >> (2 * i + h)) & 1u) {
+                double Fr[4], Hr[4];
+                const cdouble* q = cur + 16 * i + 8 * h;
+    #pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                  Fr[g] = q[g];
+                  Hr[g] = q[4 + g];
+                }
+    #pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                  const double P = fma_uniform_c(lod[4 * h + g], fk[i], Fr[g]);
+                  hot |= __builtin_amdgcn_ballot_w64(fabs(P) > Hr[g]);
+                }
+              }
+            }
+          } else if constexpr (kF64) {
     #pragma unroll
             for (int h = 0; h < 2; ++h) {
               double Fr[4], Hr[4];
@@ -2150,7 +2316,7 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
         hotm &= live;
         // a wave with fewer than TCW periods prefetched a spare row for the
         // next tile: load its first period's row again
-        if constexpr (kF64) {
+        if constexpr (kF64 && !SKIP) {
           if (ntw < TCW) {
     #pragma unroll
             for (int g = 0; g < 4; ++g) {
@@ -2184,6 +2350,9 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
               R zt = R(0), st = R(0);
     #pragma unroll
               for (int g = 0; g < 8; ++g) {
+                // a skipped half row holds no overload (and its factors were
+                // not loaded)
+                if (((need >> (2 * i + (g >> 2))) & 1u) == 0) continue;
                 // the flow formed again (the same fused operation, so the same
                 // value as in the test)
                 const R P = fma_uniform_c(lod[g], fk[i], Fr[g]);
@@ -2357,14 +2526,25 @@ int plan_batch(const Problem* const* prs, const DevWork* ws, int n, const double
   const size_t lds = (size_t)kBatchWl * kBatchTcw * 128 * sizeof(double);
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  hipError_t e;
+  // the skip test (FP64) when a problem's blocks qualify for it; the SKIP
+  // kernel tests every half row of the others
+  P.skip = false;
   if (P.lodf_kind == kLodfF64)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double>, kBatchWl * 64, lds);
+    for (int i = 0; i < n; ++i)
+      P.skip = P.skip || (prs[i]->tile.lt >= kSkipMinTiles && prs[i]->tile.lt <= 32 / kBatchTcw);
+  hipError_t e;
+  if (P.lodf_kind == kLodfF64 && P.skip)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, true>,
+                                                     kBatchWl * 64, lds);
+  else if (P.lodf_kind == kLodfF64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, false>,
+                                                     kBatchWl * 64, lds);
   else if (P.lodf_kind == kLodfF32)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<float>, kBatchWl * 64, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<float, false>,
+                                                     kBatchWl * 64, lds);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<uint16_t>, kBatchWl * 64,
-                                                     lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<uint16_t, false>,
+                                                     kBatchWl * 64, lds);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   P.pm_grid = std::max(1, std::min(P.nblk[1], ncu * per_cu));
   *plan = P;
@@ -2381,12 +2561,15 @@ int launch_eval_batch(const BatchPlan& P, void* d_buf, void* stream) {
   if (P.nblk[1] > 0) {
     const size_t lds = (size_t)kBatchWl * kBatchTcw * 128 * sizeof(double);
     const dim3 g(P.pm_grid), blk(kBatchWl * 64);
-    if (P.lodf_kind == kLodfF64)
-      hipLaunchKernelGGL(k_ctg_pm_b<double>, g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+    if (P.lodf_kind == kLodfF64 && P.skip)
+      hipLaunchKernelGGL((k_ctg_pm_b<double, true>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+    else if (P.lodf_kind == kLodfF64)
+      hipLaunchKernelGGL((k_ctg_pm_b<double, false>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
     else if (P.lodf_kind == kLodfF32)
-      hipLaunchKernelGGL(k_ctg_pm_b<float>, g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+      hipLaunchKernelGGL((k_ctg_pm_b<float, false>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
     else
-      hipLaunchKernelGGL(k_ctg_pm_b<uint16_t>, g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+      hipLaunchKernelGGL((k_ctg_pm_b<uint16_t, false>), g, blk, lds, s, args, tab(1), P.nblk[1],
+                         ctr);
   }
   if (P.nblk[2] > 0)
     hipLaunchKernelGGL(k_ctg_zred_b, dim3(P.nblk[2]), dim3(64), 0, s, args, tab(2));

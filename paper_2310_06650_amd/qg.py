@@ -44,6 +44,7 @@ QG_FLAG_CHECK_FINITE = 0x1
 QG_FLAG_CTG_FP32 = 0x2
 QG_FLAG_CTG_BF16 = 0x4
 QG_FLAG_CTG_SUM = 0x8
+QG_FLAG_CTG_NO_SKIP = 0x10
 QG_NOALLOC_SCRATCH = 32 << 20   # bytes of qg_eval_grad_noalloc's static scratch
 
 KERNEL_NAMES = ("k_forward", "k_ctg_main", "k_ctg_zred", "k_ctg_asm", "k_adjoint", "k_final")

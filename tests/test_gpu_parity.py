@@ -278,6 +278,74 @@ def test_test_radius_keeps_every_overloaded_flow(qg):
     assert checked > 1000
 
 
+def _solved_point(qg, c, steps):
+    """x after a graph-replayed solve from the flat start (a state where most
+    post-outage flows sit well inside their limits and some are overloaded)."""
+    import torch
+    prob = qg.Problem(c)
+    x = prob.new_vector(synth.flat_start(c))
+    m, v = prob.new_vector(), prob.new_vector()
+    prob.solve(x, m, v, qg.solve_opts(steps, [1e-3] * qg.QG_NCLASS, [1e-5] * qg.QG_NCLASS,
+                                      n_total=2000, eps0=1e-1, epsf=1e-4, beta0=0.1, betaf=1.0,
+                                      rho0=0.1, rhof=1.0, use_graph=1, skip_final=1))
+    torch.cuda.synchronize()
+    out = x.cpu().numpy().copy()
+    prob.close()
+    return out
+
+
+def test_skip_test_is_bitwise_exact(qg):
+    """The bound-based skip of the FP64 map-reduce passes over a half row (4
+    branches, one period, 64 contingencies) when |F_tl| + max|LODF| max|F_tk|
+    stays within the test radius.  At a state 1,500 steps into a solve of the
+    2,000-bus grid, where the bound (computed here from the oracle's flows and
+    outage factors) clears most half rows and some flows are overloaded, the
+    default problem and one built with QG_FLAG_CTG_NO_SKIP give bitwise the
+    same terms and gradient under tiles that take the skip (4 to 32 / TCW
+    branch tiles per block), and both match the oracle."""
+    c = case("c3")
+    x = _solved_point(qg, c, 1500)
+    mdl = oracle_model(c)
+    # share of half rows the bound clears (the oracle's flows, FP64)
+    V, TH, P, Q, R, U = ob.unpack(c, x)
+    q2, _ = ob.qmax2(ob.branch_flows(mdl, V, TH))
+    F = ob.balanced_injection(c, P) @ mdl.isf.T
+    T, L, K = c.n_period, c.n_branch, len(mdl.ctg)
+    Lp, Kp = -(-L // 64) * 64, -(-K // 64) * 64
+    A = np.asarray(c.br_smax_ctg, dtype=np.float64)[None, :] ** 2 - q2
+    thr = np.where(A > 0, np.sqrt(np.maximum(A, 0.0)), -1.0)
+    lod = np.abs(mdl.lodf)
+    lod[mdl.ctg, np.arange(K)] = 0.0
+    LO = np.zeros((Lp, Kp))
+    LO[:L, :K] = lod
+    lm = LO.reshape(Lp // 4, 4, Kp // 64, 64).max(axis=(1, 3))
+    fk = np.zeros((T, Kp))
+    fk[:, :K] = np.abs(F[:, mdl.ctg])
+    fkm = np.repeat(fk.reshape(T // 4, 4, Kp // 64, 64).max(axis=(1, 3)), 4, axis=0)
+    slack = np.full((T, Lp), 1.0)
+    slack[:, :L] = np.abs(F) - thr
+    cold = slack.reshape(T, Lp // 4, 4).max(axis=2)[:, :, None] + lm[None] * fkm[:, None, :] <= 0
+    assert cold.mean() > 0.5
+    smax2 = np.asarray(c.br_smax_ctg, dtype=np.float64) ** 2
+    hot = 0
+    for t in (0, 20, 40):
+        Pk = F[t][:, None] + mdl.lodf * F[t, mdl.ctg][None, :]
+        hot += int(np.nansum(Pk * Pk + q2[t][:, None] > smax2[:, None]))
+    assert hot > 0
+    tr, gr = ob.evaluate(mdl, x, 1e-4, 1.0, 1.0)
+    for tile in ("s4x4x8", "s4x3x8", "s4x2x4", "s4x2x16"):
+        got = []
+        for flags in (0, qg.QG_FLAG_CTG_NO_SKIP):
+            prob = qg.Problem(c, flags=flags)
+            prob.set_tile(tile)
+            got.append(gpu_eval(qg, prob, x, 1e-4, 1.0, 1.0))
+            prob.close()
+        (t0, g0), (t1, g1) = got
+        assert np.array_equal(t0, t1) and np.array_equal(g0, g1), tile
+        assert_terms_close(qg, t0, tr)
+        assert_grad_close(c, g0, gr)
+
+
 def test_ctg_split_tile_arguments_rejected(qg):
     prob = qg.Problem(case("c1"))
     for wl, tcw, lt in ((0, 2, 2), (9, 2, 2), (4, 0, 2), (4, 9, 2), (4, 2, 1), (4, 2, 65),
