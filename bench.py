@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--gap-steps", type=int, default=20000)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain time-to-gap leg")
-    ap.add_argument("--learned-train", type=int, default=128)
+    ap.add_argument("--learned-train", type=int, default=512)
     ap.add_argument("--learned-test", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this size "
@@ -323,7 +323,7 @@ def main():
     if not args.no_gap:
         out["gap"] = plain_gap(qg, synth, prob, case, args.gap_steps)
     if not args.no_learned and args.config == "c2":
-        out["learned_gap"] = learned_gap(case, args.learned_train, args.learned_test, 8000, 800)
+        out["learned_gap"] = learned_gap(case, args.learned_train, args.learned_test, 8000, 1500)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda:0")
