@@ -55,13 +55,17 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 
 // C (+ z * M * ldc) = op(A) op(B) over the z-th reduction slice.
 // op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k]; op(B)[k][n] likewise.
+// Software-pipelined: the operands of the next 16-wide k-step are loaded
+// into registers while the current one is multiplied from one of two LDS
+// buffers (one barrier per k-step: a buffer is refilled only after every
+// wavefront has passed the barrier that follows its last use).
 template <int TA, int TB>
 __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float* __restrict__ A, int lda,
                                                       const float* __restrict__ B, int ldb,
                                                       float* __restrict__ C, int ldc, int M,
                                                       int N, int K, int kslice) {
-  __shared__ float As[kT][17];
-  __shared__ float Bs[16][kT + 1];
+  __shared__ float As[2][kT][17];
+  __shared__ float Bs[2][16][kT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * kT, n0 = blockIdx.x * kT;
   const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
@@ -71,40 +75,46 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float* __restrict__
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  float ra[4], rb[4];  // this thread's elements of the next k-step
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * kThreads;
       const int mm = TA ? (e & 63) : (e >> 4), kk = TA ? (e >> 6) : (e & 15);
       const int gm = m0 + mm, gk = k0 + kk;
-      float v = 0.f;
-      if (gm < M && gk < ke) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-      As[mm][kk] = v;
+      ra[q] = (gm < M && gk < ke) ? (TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]) : 0.f;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * kThreads;
       const int kk = TB ? (e & 15) : (e >> 6), nn = TB ? (e >> 4) : (e & 63);
       const int gk = k0 + kk, gn = n0 + nn;
-      float v = 0.f;
-      if (gn < N && gk < ke) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-      Bs[kk][nn] = v;
+      rb[q] = (gn < N && gk < ke) ? (TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn]) : 0.f;
+    }
+  };
+  if (kb < ke) gload(kb);
+  for (int k0 = kb, buf = 0; k0 < ke; k0 += 16, buf ^= 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * kThreads;
+      As[buf][TA ? (e & 63) : (e >> 4)][TA ? (e >> 6) : (e & 15)] = ra[q];
+      Bs[buf][TB ? (e & 15) : (e >> 6)][TB ? (e >> 4) : (e & 63)] = rb[q];
     }
     __syncthreads();
+    if (k0 + 16 < ke) gload(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
+      for (int i = 0; i < 2; ++i) a[i] = As[buf][wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
   float* Cz = C + (size_t)blockIdx.z * M * ldc;
 #pragma unroll
@@ -119,13 +129,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float* __restrict__
       }
 }
 
-// BF16 operands, row-major A [M][K] and B [K][N], FP32 sums.
+// BF16 operands, row-major A [M][K] and B [K][N], FP32 sums; pipelined like
+// k_gemm_f32 with 32-wide k-steps.
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const uint16_t* __restrict__ A, int lda,
                                                        const uint16_t* __restrict__ B, int ldb,
                                                        float* __restrict__ C, int ldc, int M,
                                                        int N, int K, int kslice) {
-  __shared__ uint16_t As[kT][32 + 8];  // [m][k]
-  __shared__ uint16_t Bs[kT][32 + 8];  // [n][k] (transposed for 8 consecutive k per lane)
+  __shared__ uint16_t As[2][kT][32 + 8];  // [m][k]
+  __shared__ uint16_t Bs[2][kT][32 + 8];  // [n][k] (transposed for 8 consecutive k per lane)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * kT, n0 = blockIdx.x * kT;
   const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
@@ -135,32 +146,43 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const uint16_t* __restri
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += 32) {
+  uint16_t ra[8], rb[8];
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = tid + q * kThreads;  // 64 x 32 tile
       const int mm = e >> 5, kk = e & 31;
       const int gm = m0 + mm, gk = k0 + kk;
-      As[mm][kk] = (gm < M && gk < ke) ? A[(size_t)gm * lda + gk] : (uint16_t)0;
+      ra[q] = (gm < M && gk < ke) ? A[(size_t)gm * lda + gk] : (uint16_t)0;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = tid + q * kThreads;  // 32 x 64 tile, coalesced along n
       const int kk = e >> 6, nn = e & 63;
       const int gk = k0 + kk, gn = n0 + nn;
-      Bs[nn][kk] = (gn < N && gk < ke) ? B[(size_t)gk * ldb + gn] : (uint16_t)0;
+      rb[q] = (gn < N && gk < ke) ? B[(size_t)gk * ldb + gn] : (uint16_t)0;
+    }
+  };
+  if (kb < ke) gload(kb);
+  for (int k0 = kb, buf = 0; k0 < ke; k0 += 32, buf ^= 1) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + q * kThreads;
+      As[buf][e >> 5][e & 31] = ra[q];
+      Bs[buf][e & 63][e >> 6] = rb[q];
     }
     __syncthreads();
+    if (k0 + 32 < ke) gload(k0 + 32);
     v8bf a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const uint16_t* src = &As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)];
+      const uint16_t* src = &As[buf][wm + i * 16 + (lane & 15)][8 * (lane >> 4)];
 #pragma unroll
       for (int u = 0; u < 8; ++u) a[i][u] = __builtin_bit_cast(__bf16, src[u]);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const uint16_t* src = &Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)];
+      const uint16_t* src = &Bs[buf][wn + j * 16 + (lane & 15)][8 * (lane >> 4)];
 #pragma unroll
       for (int u = 0; u < 8; ++u) b[j][u] = __builtin_bit_cast(__bf16, src[u]);
     }
@@ -169,7 +191,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const uint16_t* __restri
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
   }
   float* Cz = C + (size_t)blockIdx.z * M * ldc;
 #pragma unroll
@@ -193,13 +214,28 @@ struct EpiArgs {
   uint16_t* out16;    // kBiasGeluBf16
 };
 
+// The slices of 32 elements are summed by 8 groups of threads (group g takes
+// slices g, g + 8, ...), the group sums then added in group order: a fixed
+// order, with 8 independent chains of loads in flight per element.
 __global__ __launch_bounds__(kThreads) void k_reduce_epi(const float* __restrict__ P, int slices,
                                                          int M, int N, EpiArgs ep) {
+  __shared__ float red[8][33];
   const size_t MN = (size_t)M * N;
-  for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < MN;
-       e += (size_t)gridDim.x * kThreads) {
+  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+  for (size_t e0 = (size_t)blockIdx.x * 32; e0 < MN; e0 += (size_t)gridDim.x * 32) {
+    const size_t ec = e0 + c;
+    float part = 0.f;
+    if (ec < MN)
+      for (int q = g; q < slices; q += 8) part += P[(size_t)q * MN + ec];
+    red[g][c] = part;
+    __syncthreads();
+    const size_t e = ec;
+    const bool mine = g == 0 && e < MN;
     float s = 0.f;
-    for (int q = 0; q < slices; ++q) s += P[(size_t)q * MN + e];
+    if (mine)
+      for (int q = 0; q < 8; ++q) s += red[q][c];
+    __syncthreads();  // red is refilled by the next round
+    if (!mine) continue;
     const int n = (int)(e % N);
     switch (ep.kind) {
       case kBiasGelu: {
@@ -216,14 +252,20 @@ __global__ __launch_bounds__(kThreads) void k_reduce_epi(const float* __restrict
   }
 }
 
-// db[n] = sum_m dZ[m][n] (rows in order)
+// db[n] = sum_m dZ[m][n]: 64 columns a block, each column's rows in four
+// interleaved quarters (thread q takes rows q, q + 4, ...), the quarters
+// then added in order
 __global__ __launch_bounds__(kThreads) void k_colsum(const float* __restrict__ dZ, int M, int N,
                                                      float* __restrict__ db) {
-  const int n = blockIdx.x * kThreads + threadIdx.x;
-  if (n >= N) return;
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += dZ[(size_t)m * N + n];
-  db[n] = s;
+  if (n < N)
+    for (int m = q; m < M; m += 4) s += dZ[(size_t)m * N + n];
+  red[q][c] = s;
+  __syncthreads();
+  if (q == 0 && n < N) db[n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
 // dY = 2 (Y - T) / (M N); per-block partial sums of (Y - T)^2
@@ -247,12 +289,17 @@ __global__ __launch_bounds__(kThreads) void k_mse(const float* __restrict__ Y,
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_loss_final(const float* __restrict__ part, int n, float inv, float* loss) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    float s = 0.f;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *loss = s * inv;
+// loss = inv * sum of the n <= kThreads block partials, by a tree in a fixed order
+__global__ __launch_bounds__(kThreads) void k_loss_final(const float* __restrict__ part, int n,
+                                                         float inv, float* loss) {
+  __shared__ float red[kThreads];
+  red[threadIdx.x] = (int)threadIdx.x < n ? part[threadIdx.x] : 0.f;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *loss = red[0] * inv;
 }
 
 __global__ __launch_bounds__(kThreads) void k_adam_f32(float* __restrict__ p, float* __restrict__ m,
@@ -300,7 +347,7 @@ struct Ws {
   size_t total;
 };
 
-constexpr int kMaxSlices = 32;
+constexpr int kMaxSlices = 128;
 
 bool valid(const qg_mlp_desc* d) {
   return d && d->d_in > 0 && d->width > 0 && d->d_out > 0 && d->depth >= 1 &&
@@ -324,11 +371,12 @@ void layout(const qg_mlp_desc* d, qg_mlp_layout* L) {
   L->n_params = o;
 }
 
-// product slices: enough blocks for the chip when the output has few tiles
+// product slices: about four blocks per CU when the output has few tiles,
+// each slice at least 32 deep (the pipelined k-loop needs a few k-steps)
 int slices_for(int M, int N, int K) {
   const int tiles = ((M + kT - 1) / kT) * ((N + kT - 1) / kT);
   int s = 1;
-  while (s < kMaxSlices && tiles * s < 512 && K / (s * 2) >= 256) s *= 2;
+  while (s < kMaxSlices && tiles * s < 1024 && K / (s * 2) >= 32) s *= 2;
   return s;
 }
 
@@ -362,6 +410,8 @@ Ws carve(const qg_mlp_desc* d, int B, void* base) {
 }
 
 int grid1(size_t n) { return (int)std::min<size_t>(4096, (n + kThreads - 1) / kThreads); }
+// k_reduce_epi: 32 elements a block and round
+int grid_red(size_t n) { return (int)std::min<size_t>(4096, (n + 31) / 32); }
 
 // C = op(A) op(B) with epilogue; slices go through ws.part
 int fit_slices(int sl, int M, int N, const Ws& w) {
@@ -381,8 +431,8 @@ hipError_t product(hipStream_t s, int ta, int tb, const float* A, int lda, const
   else if (!ta && tb) hipLaunchKernelGGL((k_gemm_f32<0, 1>), grid, dim3(kThreads), 0, s, A, lda, B, ldb, dst, N, M, N, K, kslice);
   else hipLaunchKernelGGL((k_gemm_f32<1, 1>), grid, dim3(kThreads), 0, s, A, lda, B, ldb, dst, N, M, N, K, kslice);
   if (!direct)
-    hipLaunchKernelGGL(k_reduce_epi, dim3(grid1((size_t)M * N)), dim3(kThreads), 0, s, w.part, sl,
-                       M, N, ep);
+    hipLaunchKernelGGL(k_reduce_epi, dim3(grid_red((size_t)M * N)), dim3(kThreads), 0, s, w.part,
+                       sl, M, N, ep);
   return hipGetLastError();
 }
 
@@ -393,8 +443,8 @@ hipError_t product16(hipStream_t s, const uint16_t* A, int lda, const uint16_t* 
   const dim3 grid((N + kT - 1) / kT, (M + kT - 1) / kT, sl);
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(kThreads), 0, s, A, lda, B, ldb, w.part, N, M, N, K,
                      kslice);
-  hipLaunchKernelGGL(k_reduce_epi, dim3(grid1((size_t)M * N)), dim3(kThreads), 0, s, w.part, sl, M,
-                     N, ep);
+  hipLaunchKernelGGL(k_reduce_epi, dim3(grid_red((size_t)M * N)), dim3(kThreads), 0, s, w.part, sl,
+                     M, N, ep);
   return hipGetLastError();
 }
 
@@ -472,7 +522,8 @@ qg_status qg_mlp_grad(const qg_mlp_desc* desc, const float* d_params, const floa
   const float inv = 1.0f / (float)BO;
   hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kThreads), 0, s, w.y, d_t, BO, inv, w.dy,
                      w.loss_part);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, w.loss_part, kLossBlocks, inv, d_loss);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kThreads), 0, s, w.loss_part, kLossBlocks, inv,
+                     d_loss);
   // output layer: dW_out = h_D^T dY, db_out = colsum dY, dh_D = dY W_out^T
   const float* dcur = w.dy;  // gradient at the current layer's output
   int n_out = desc->d_out;
@@ -482,8 +533,8 @@ qg_status qg_mlp_grad(const qg_mlp_desc* desc, const float* d_params, const floa
     EpiArgs ew{kStore, nullptr, nullptr, d_grad + L.w_off[i], nullptr};
     e = product(s, 1, 0, in, fan_in, dcur, n_out, fan_in, n_out, B, ew, w);
     if (e != hipSuccess) return dev_fail(e, "mlp weight gradient");
-    hipLaunchKernelGGL(k_colsum, dim3((n_out + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                       dcur, B, n_out, d_grad + L.b_off[i]);
+    hipLaunchKernelGGL(k_colsum, dim3((n_out + 63) / 64), dim3(kThreads), 0, s, dcur, B, n_out,
+                       d_grad + L.b_off[i]);
     if (i == 0) break;
     // dz_{i-1} = (dcur W_i^T) * gelu'(z_{i-1}), W_i is [fan_in][n_out]
     float* dst = (dcur == w.dz) ? w.da : w.dz;
