@@ -53,6 +53,20 @@ def assert_grad_close(case, g, g_ref, tol=TOL):
         assert err <= tol, (name, err, den)
 
 
+def assert_grad_close_elementwise(case, g, g_ref, rel=TOL, floor=1e-14):
+    """Every entry: |g - g*| <= rel |g*| + floor max|g*| of its class.  Holds
+    at interior points away from the kinks, where the terms of a gradient
+    entry do not cancel heavily; near a solved point (small eps, large
+    penalty terms cancelling) only the normwise bound above is kept."""
+    names = ("v", "theta", "p", "q", "r", "u")
+    for name, s in zip(names, case.block_slices()):
+        scale = np.abs(g_ref[s]).max()
+        err = np.abs(g[s] - g_ref[s])
+        bound = rel * np.abs(g_ref[s]) + floor * scale
+        bad = np.nonzero(err > bound)[0]
+        assert bad.size == 0, (name, int(bad[0]), g[s][bad[0]], g_ref[s][bad[0]], scale)
+
+
 def gpu_eval(qg, prob, x, eps, beta, rho):
     import torch
     xd = prob.new_vector(x)
@@ -80,6 +94,7 @@ def test_terms_and_gradient_c1(qg, seed, eps, beta, rho):
     tr, gr = ob.evaluate(oracle_model(c), x, eps, beta, rho)
     assert_terms_close(qg, t, tr)
     assert_grad_close(c, g, gr)
+    assert_grad_close_elementwise(c, g, gr)
 
 
 @pytest.mark.parametrize("which", ["random", "flat"])
@@ -91,6 +106,7 @@ def test_terms_and_gradient_c2(qg, which):
     tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 0.8, 1.0)
     assert_terms_close(qg, t, tr)
     assert_grad_close(c, g, gr)
+    assert_grad_close_elementwise(c, g, gr)
 
 
 def test_terms_and_gradient_c3(qg):
@@ -102,6 +118,7 @@ def test_terms_and_gradient_c3(qg):
     tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
     assert_terms_close(qg, t, tr)
     assert_grad_close(c, g, gr)
+    assert_grad_close_elementwise(c, g, gr)
 
 
 def test_intermediates_c2(qg):
