@@ -820,8 +820,9 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
   mfma_slab<1, 8>(aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
 }
 
-// Blocks [0, nb_br): branch forward; [nb_br, nb_br + T): one period each;
-// then (Lp / 16) x (Tp / 16) flow slabs.
+// Blocks [0, T): one period each (the longest chains of the kernel, so they
+// are dispatched first); [T, T + nb_br): branch forward; then (Lp / 16) x
+// (Tp / 16) flow slabs.
 __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* smem) {
   StepParams sp;
   resolve_params(a, sp);
@@ -834,10 +835,10 @@ __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* s
     pb[PB_BC1] = sp.bc1;
     pb[PB_BC2] = sp.bc2;
   }
-  if (b < a.nb_br)
-    branch_forward(a, sp, b, smem);
+  if (b < a.p.T)
+    period_block(a, sp, b, smem);
   else if (b < a.nb_br + a.p.T)
-    period_block(a, sp, b - a.nb_br, smem);
+    branch_forward(a, sp, b - a.p.T, smem);
   else
     flow_slab(a, b - a.nb_br - a.p.T, smem);
 }
