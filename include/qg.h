@@ -94,7 +94,7 @@ enum { QG_CTG_ALL_NONBRIDGE = 0, QG_CTG_LIST = 1 };
  * QG_T_CTG_MAX is 0. */
 #define QG_FLAG_CTG_SUM 0x8u
 /* Bound-based skip of the FP64 contingency map-reduce.  Default: with FP64
- * outage factors, every contingency scored and blocks of 4 to 32 / (periods
+ * outage factors, every contingency scored and blocks of 4 to 64 / (periods
  * per wavefront) branch tiles, a half row (4 branches, one period, 64
  * contingencies) is passed over when |F_tl| + max|LODF_lk| max|F_tk| proves
  * every post-outage flow within its test radius (with margins that cover the

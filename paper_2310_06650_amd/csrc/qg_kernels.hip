@@ -1203,21 +1203,25 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
   uint64_t fbits = 0;
   // SKIP: half rows proved free of overloads are skipped (ctg_cold_mask),
   // with FP64 factors, every contingency scored and a block of at most
-  // 32 / TCW tiles (one mask covers them all; the host launches the SKIP
-  // form only then, and a block outside it tests everything); the F and
-  // thr of a tested half row are loaded when it is reached.  Otherwise they
-  // are prefetched one half row ahead.
-  // bit (ti TCW + i) 2 + h: half row h of period tw + i of tile ti skipped
-  uint64_t coldm = 0;
+  // 64 / TCW tiles (two masks of 32 / TCW tiles cover them; the host
+  // launches the SKIP form only then, and a block outside it tests
+  // everything); the F and thr of a tested half row are loaded when it is
+  // reached.  Otherwise they are prefetched one half row ahead.
+  // Bit ((ti mod CT) TCW + i) 2 + h of mask ti / CT (CT = 32 / TCW): half
+  // row h of period tw + i of tile ti skipped.
+  uint64_t coldm = 0, coldm1 = 0;
   if constexpr (SKIP) {
     constexpr int CT = 32 / TCW;  // tiles per mask
     const int ntile = (l1 - l0) >> 3;
-    if (p.lmaxh != nullptr && a.act_k == nullptr && ntile <= CT) {
+    if (p.lmaxh != nullptr && a.act_k == nullptr && ntile <= 2 * CT) {
       double fkm = 0.0;  // largest |F_tk| of the wave's lanes and periods
 #pragma unroll
       for (int i = 0; i < TCW; ++i) fkm = fmax(fkm, fabs(fk[i]));
       fkm = wave_max(fkm);
       coldm = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6, fkm);
+      if (ntile > CT)
+        coldm1 = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, (l0 >> 3) + CT, ntile - CT, kb,
+                                    Kp >> 6, fkm);
     }
   }
   // F and thr of the next half row (four branches of one period) to be
@@ -1246,7 +1250,9 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
     const cdouble* nxt = cur + fstep;
     // the tile's half rows that are tested (bit 2 i + h); a tile without
     // any is passed over, and only the factor rows of tested halves are loaded
-    const uint32_t need = ~(uint32_t)(coldm >> (ti * TCW * 2)) & ((1u << (2 * TCW)) - 1u);
+    const uint32_t need =
+        ~(uint32_t)((ti < 32 / TCW ? coldm : coldm1) >> ((ti % (32 / TCW)) * TCW * 2)) &
+        ((1u << (2 * TCW)) - 1u);
     if (need == 0) continue;
     R lod[8];
 #pragma unroll
@@ -1938,11 +1944,11 @@ void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArg
 }
 
 // The map-reduce takes the skip test (ctg_cold_mask) with FP64 factors,
-// every contingency scored and blocks of 4 to 32 / TCW branch tiles: with
+// every contingency scored and blocks of 4 to 64 / TCW branch tiles: with
 // fewer tiles per block the mask's cost is not recovered.
 constexpr int kSkipMinTiles = 4;
 inline bool ctg_skip(const EvalArgs& a, int tcw) {
-  return a.p.lmaxh != nullptr && a.act_k == nullptr && a.lt >= kSkipMinTiles && a.lt <= 32 / tcw;
+  return a.p.lmaxh != nullptr && a.act_k == nullptr && a.lt >= kSkipMinTiles && a.lt <= 64 / tcw;
 }
 
 template <int TCW, typename LT>
@@ -2194,21 +2200,25 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
       uint64_t fbits = 0;
       // SKIP: half rows proved free of overloads are skipped (ctg_cold_mask),
       // with FP64 factors, every contingency scored and a block of at most
-      // 32 / TCW tiles (one mask covers them all; the host launches the SKIP
-      // form only then, and a block outside it tests everything); the F and
-      // thr of a tested half row are loaded when it is reached.  Otherwise they
-      // are prefetched one half row ahead.
-      // bit (ti TCW + i) 2 + h: half row h of period tw + i of tile ti skipped
-      uint64_t coldm = 0;
+      // 64 / TCW tiles (two masks of 32 / TCW tiles cover them; the host
+      // launches the SKIP form only then, and a block outside it tests
+      // everything); the F and thr of a tested half row are loaded when it is
+      // reached.  Otherwise they are prefetched one half row ahead.
+      // Bit ((ti mod CT) TCW + i) 2 + h of mask ti / CT (CT = 32 / TCW): half
+      // row h of period tw + i of tile ti skipped.
+      uint64_t coldm = 0, coldm1 = 0;
       if constexpr (SKIP) {
         constexpr int CT = 32 / TCW;  // tiles per mask
         const int ntile = (l1 - l0) >> 3;
-        if (p.lmaxh != nullptr && a.act_k == nullptr && ntile <= CT) {
+        if (p.lmaxh != nullptr && a.act_k == nullptr && ntile <= 2 * CT) {
           double fkm = 0.0;  // largest |F_tk| of the wave's lanes and periods
     #pragma unroll
           for (int i = 0; i < TCW; ++i) fkm = fmax(fkm, fabs(fk[i]));
           fkm = wave_max(fkm);
           coldm = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6, fkm);
+          if (ntile > CT)
+            coldm1 = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, (l0 >> 3) + CT, ntile - CT, kb,
+                                        Kp >> 6, fkm);
         }
       }
       // F and thr of the next half row (four branches of one period) to be
@@ -2237,7 +2247,9 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
         const cdouble* nxt = cur + fstep;
         // the tile's half rows that are tested (bit 2 i + h); a tile without
         // any is passed over, and only the factor rows of tested halves are loaded
-        const uint32_t need = ~(uint32_t)(coldm >> (ti * TCW * 2)) & ((1u << (2 * TCW)) - 1u);
+        const uint32_t need =
+            ~(uint32_t)((ti < 32 / TCW ? coldm : coldm1) >> ((ti % (32 / TCW)) * TCW * 2)) &
+            ((1u << (2 * TCW)) - 1u);
         if (need == 0) continue;
         R lod[8];
     #pragma unroll
@@ -2532,7 +2544,7 @@ int plan_batch(const Problem* const* prs, const DevWork* ws, int n, const double
   P.skip = false;
   if (P.lodf_kind == kLodfF64)
     for (int i = 0; i < n; ++i)
-      P.skip = P.skip || (prs[i]->tile.lt >= kSkipMinTiles && prs[i]->tile.lt <= 32 / kBatchTcw);
+      P.skip = P.skip || (prs[i]->tile.lt >= kSkipMinTiles && prs[i]->tile.lt <= 64 / kBatchTcw);
   hipError_t e;
   if (P.lodf_kind == kLodfF64 && P.skip)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, true>,
