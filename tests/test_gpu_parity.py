@@ -318,8 +318,9 @@ def test_skip_test_is_bitwise_exact(qg):
     2,000-bus grid, where the bound (computed here from the oracle's flows and
     outage factors) clears most half rows and some flows are overloaded, the
     default problem and one built with QG_FLAG_CTG_NO_SKIP give bitwise the
-    same terms and gradient under tiles that take the skip (4 to 32 / TCW
-    branch tiles per block), and both match the oracle."""
+    same terms and gradient under tiles that take the skip (4 to 64 / TCW
+    branch tiles per block, one or two masks a wavefront), and both match the
+    oracle."""
     c = case("c3")
     x = _solved_point(qg, c, 1500)
     mdl = oracle_model(c)
@@ -350,7 +351,7 @@ def test_skip_test_is_bitwise_exact(qg):
         hot += int(np.nansum(Pk * Pk + q2[t][:, None] > smax2[:, None]))
     assert hot > 0
     tr, gr = ob.evaluate(mdl, x, 1e-4, 1.0, 1.0)
-    for tile in ("s4x4x8", "s4x3x8", "s4x2x4", "s4x2x16"):
+    for tile in ("s4x4x8", "s4x3x8", "s4x2x4", "s4x2x16", "s4x4x16", "s2x4x12"):
         got = []
         for flags in (0, qg.QG_FLAG_CTG_NO_SKIP):
             prob = qg.Problem(c, flags=flags)
