@@ -636,16 +636,27 @@ qg_status build_arena(const qg_grid_desc* d, const qg_build_opts* o, Problem* p,
       }
     });
     // largest |factor| of every 4-branch group over every 64-contingency
-    // block (NaN entries left out): the bound of the map-reduce's skip test
+    // block (NaN entries left out), of the factors as stored (FP32 or BF16
+    // rounding included): the bound of the map-reduce's skip test
     {
       double* lm = reinterpret_cast<double*>(img.data() + cl.off[46]);
       const int nkb = Kp / 64;
+      auto stored = [&](double v) -> double {
+        if (kind == kLodfF32) return (double)(float)v;
+        if (kind == kLodfBF16) {
+          const uint32_t u = (uint32_t)to_bf16((float)v) << 16;
+          float f;
+          std::memcpy(&f, &u, 4);
+          return (double)f;
+        }
+        return v;
+      };
       parallel_for(Lp / 4, [&](int q) {
         for (int kb = 0; kb < nkb; ++kb) {
           double m = 0.0;
           for (int l = 4 * q; l < 4 * q + 4; ++l)
             for (int k = 64 * kb; k < 64 * kb + 64; ++k) {
-              const double v = std::fabs(lo[(size_t)l * Kp + k]);
+              const double v = std::fabs(stored(lo[(size_t)l * Kp + k]));
               if (v > m) m = v;  // false for NaN
             }
           lm[(size_t)q * nkb + kb] = m;
@@ -730,7 +741,7 @@ void rebase_pointers(Problem* p, void* arena) {
   dp.lodf_kind = lodf_kind_of(p->flags);
   dp.ctg_sum = (p->flags & QG_FLAG_CTG_SUM) ? 1 : 0;
   dp.lodf = dp.lodf_kind == kLodfF64 ? D(43) : nullptr;
-  dp.lmaxh = dp.lodf_kind == kLodfF64 && !(p->flags & QG_FLAG_CTG_NO_SKIP) ? D(46) : nullptr;
+  dp.lmaxh = !(p->flags & QG_FLAG_CTG_NO_SKIP) ? D(46) : nullptr;
   dp.lodf32 = dp.lodf_kind == kLodfF32 ? reinterpret_cast<const float*>(base + cl.off[43]) : nullptr;
   dp.lodf16 =
       dp.lodf_kind == kLodfBF16 ? reinterpret_cast<const uint16_t*>(base + cl.off[43]) : nullptr;

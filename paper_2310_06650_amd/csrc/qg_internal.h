@@ -73,8 +73,8 @@ struct DevProblem {
   const float* lodf32;   //           the same in FP32 (QG_FLAG_CTG_FP32)
   const uint16_t* lodf16;  //         the same in BF16 (QG_FLAG_CTG_BF16)
   int lodf_kind;         // 0 FP64, 1 FP32, 2 BF16 (one of the three pointers is set)
-  const double* lmaxh;   // [Lp/4][Kp/64] max |lodf| of each 4-branch group and 64-contingency
-                         // block, NaN left out (FP64 factors only, else null)
+  const double* lmaxh;   // [Lp/4][Kp/64] max |lodf| (as stored) of each 4-branch group and
+                         // 64-contingency block, NaN left out (null with QG_FLAG_CTG_NO_SKIP)
   int ctg_sum;           // 1: per-period sum over contingencies instead of max + mean
   // prices
   double c_p, c_q, c_s, c_ang, ang_max, c_rsv, rho, vload;

@@ -1092,11 +1092,20 @@ __global__ __launch_bounds__(512) void k_ctg_main(EvalArgs a, const LT* __restri
 // e of the wavefront decides half row (period tw + i, tile t0 + j) with
 // j = e / (2 TCW), i = (e / 2) % TCW, h = e % 2; periods past the wave's last
 // are skipped (their verdicts are dropped anyway).  Returns the ballot.
-template <int TCW>
+//
+// FP32 arithmetic (FP32 or BF16 factors) tests fl(P^2 + qmax2) > s_ctg^2 in
+// FP32 on FP32 roundings of F, qmax2 and s_ctg^2, and Lm is the largest
+// stored factor.  There |fl(P)| <= (Lm Fm + |F|)(1 + u)^2 and the test's
+// left side is at most ((Lm Fm + |F|)^2 + qmax2)(1 + u)^5 (u = 2^-24), so a
+// half row is skipped when (Lm Fm + |F|)^2 (1 + 2^-18) + qmax2 (1 + 2^-18)
+// <= s_ctg^2 (1 - 2^-18), computed in FP64, for each of its branches.
+template <int TCW, bool F64>
 __device__ __forceinline__ uint64_t ctg_cold_mask(const double* __restrict__ fh,
                                                   const double* __restrict__ lmaxh, int T,
                                                   int tw, int ntw, int tile0, int ntile, int kb,
-                                                  int nkb, double fkm) {
+                                                  int nkb, double fkm,
+                                                  const double* __restrict__ q2,
+                                                  const double* __restrict__ smax2, int Lp) {
   constexpr int CT = 32 / TCW;  // tiles per mask
   const int e = threadIdx.x & 63;
   const int j = e / (2 * TCW), i = (e >> 1) % TCW, h = e & 1;
@@ -1115,10 +1124,20 @@ __device__ __forceinline__ uint64_t ctg_cold_mask(const double* __restrict__ fh,
         t[g] = r[4 + g];
       }
       cold = true;
+      if constexpr (F64) {
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const double s = fabs(f[g]) * (1.0 + 0x1p-40) - t[g] * (1.0 - 0x1p-40);
-        cold = cold && fma(lm, fkm, s) <= 0.0;
+        for (int g = 0; g < 4; ++g) {
+          const double s = fabs(f[g]) * (1.0 + 0x1p-40) - t[g] * (1.0 - 0x1p-40);
+          cold = cold && fma(lm, fkm, s) <= 0.0;
+        }
+      } else {
+        const int l = tile * 8 + 4 * h;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const double b = fma(lm, fkm, fabs(f[g]));
+          const double lhs = (b * b + q2[(size_t)(tw + i) * Lp + l + g]) * (1.0 + 0x1p-18);
+          cold = cold && lhs <= smax2[l + g] * (1.0 - 0x1p-18);
+        }
       }
     }
   }
@@ -1154,7 +1173,6 @@ template <int TCW, typename LT, bool SKIP>
 __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict__ lodf) {
   typedef typename std::conditional<std::is_same<LT, double>::value, double, float>::type R;
   constexpr bool kF64 = std::is_same<R, double>::value;
-  static_assert(kF64 || !SKIP, "the skip test bounds FP64 factors");
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int lane = threadIdx.x & 63;
@@ -1218,10 +1236,11 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
       for (int i = 0; i < TCW; ++i) fkm = fmax(fkm, fabs(fk[i]));
       fkm = wave_max(fkm);
-      coldm = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6, fkm);
+      coldm = ctg_cold_mask<TCW, kF64>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6,
+                                       fkm, w.q2, p.ctg_smax2, Lp);
       if (ntile > CT)
-        coldm1 = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, (l0 >> 3) + CT, ntile - CT, kb,
-                                    Kp >> 6, fkm);
+        coldm1 = ctg_cold_mask<TCW, kF64>(w.fh, p.lmaxh, T, tw, ntw, (l0 >> 3) + CT, ntile - CT,
+                                          kb, Kp >> 6, fkm, w.q2, p.ctg_smax2, Lp);
     }
   }
   // F and thr of the next half row (four branches of one period) to be
@@ -1276,7 +1295,7 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
 #pragma unroll
     for (int i = 0; i < TCW; ++i) {
       uint64_t hot = 0;
-      if constexpr (SKIP) {
+      if constexpr (SKIP && kF64) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           if ((need >> (2 * i + h)) & 1u) {
@@ -1319,12 +1338,19 @@ __global__ __launch_bounds__(512) void k_ctg_pm(EvalArgs a, const LT* __restrict
           }
         }
       } else {
+        // FP32 arithmetic; with SKIP only the half rows that are tested
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          const R Fr = readlane_any(fv, i * 8 + g);
-          const R P = fma_uniform_c(lod[g], fk[i], Fr);
-          const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
-          hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+        for (int h = 0; h < 2; ++h) {
+          if ((need >> (2 * i + h)) & 1u) {
+#pragma unroll
+            for (int gg = 0; gg < 4; ++gg) {
+              const int g = 4 * h + gg;
+              const R Fr = readlane_any(fv, i * 8 + g);
+              const R P = fma_uniform_c(lod[g], fk[i], Fr);
+              const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
+              hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+            }
+          }
         }
       }
       hotm |= (hot != 0 ? 1u : 0u) << i;
@@ -1943,9 +1969,9 @@ void launch_ctg_main(int bl, dim3 grid, dim3 block, hipStream_t s, const EvalArg
   }
 }
 
-// The map-reduce takes the skip test (ctg_cold_mask) with FP64 factors,
-// every contingency scored and blocks of 4 to 64 / TCW branch tiles: with
-// fewer tiles per block the mask's cost is not recovered.
+// The map-reduce takes the skip test (ctg_cold_mask) with every contingency
+// scored and blocks of 4 to 64 / TCW branch tiles: with fewer tiles per
+// block the mask's cost is not recovered.
 constexpr int kSkipMinTiles = 4;
 inline bool ctg_skip(const EvalArgs& a, int tcw) {
   return a.p.lmaxh != nullptr && a.act_k == nullptr && a.lt >= kSkipMinTiles && a.lt <= 64 / tcw;
@@ -1955,11 +1981,9 @@ template <int TCW, typename LT>
 void launch_ctg_pm_t(dim3 grid, dim3 block, hipStream_t s, const EvalArgs& a, const LT* lodf) {
   // z and S of every (wavefront, period, lane)
   const size_t lds = (size_t)(block.x / 64) * TCW * 128 * sizeof(double);
-  if constexpr (std::is_same<LT, double>::value) {
-    if (ctg_skip(a, TCW)) {
-      hipLaunchKernelGGL((k_ctg_pm<TCW, LT, true>), grid, block, lds, s, a, lodf);
-      return;
-    }
+  if (ctg_skip(a, TCW)) {
+    hipLaunchKernelGGL((k_ctg_pm<TCW, LT, true>), grid, block, lds, s, a, lodf);
+    return;
   }
   hipLaunchKernelGGL((k_ctg_pm<TCW, LT, false>), grid, block, lds, s, a, lodf);
 }
@@ -2215,10 +2239,11 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
     #pragma unroll
           for (int i = 0; i < TCW; ++i) fkm = fmax(fkm, fabs(fk[i]));
           fkm = wave_max(fkm);
-          coldm = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6, fkm);
+          coldm = ctg_cold_mask<TCW, kF64>(w.fh, p.lmaxh, T, tw, ntw, l0 >> 3, ntile, kb, Kp >> 6,
+                                           fkm, w.q2, p.ctg_smax2, Lp);
           if (ntile > CT)
-            coldm1 = ctg_cold_mask<TCW>(w.fh, p.lmaxh, T, tw, ntw, (l0 >> 3) + CT, ntile - CT, kb,
-                                        Kp >> 6, fkm);
+            coldm1 = ctg_cold_mask<TCW, kF64>(w.fh, p.lmaxh, T, tw, ntw, (l0 >> 3) + CT, ntile - CT,
+                                              kb, Kp >> 6, fkm, w.q2, p.ctg_smax2, Lp);
         }
       }
       // F and thr of the next half row (four branches of one period) to be
@@ -2273,7 +2298,7 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
     #pragma unroll
         for (int i = 0; i < TCW; ++i) {
           uint64_t hot = 0;
-          if constexpr (SKIP) {
+          if constexpr (SKIP && kF64) {
     #pragma unroll
             for (int h = 0; h < 2; ++h) {
               if ((need >> (2 * i + h)) & 1u) {
@@ -2316,12 +2341,19 @@ __global__ __launch_bounds__(kBatchWl * 64) void k_ctg_pm_b(const EvalArgs* __re
               }
             }
           } else {
+            // FP32 arithmetic; with SKIP only the half rows that are tested
     #pragma unroll
-            for (int g = 0; g < 8; ++g) {
-              const R Fr = readlane_any(fv, i * 8 + g);
-              const R P = fma_uniform_c(lod[g], fk[i], Fr);
-              const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
-              hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+            for (int h = 0; h < 2; ++h) {
+              if ((need >> (2 * i + h)) & 1u) {
+    #pragma unroll
+                for (int gg = 0; gg < 4; ++gg) {
+                  const int g = 4 * h + gg;
+                  const R Fr = readlane_any(fv, i * 8 + g);
+                  const R P = fma_uniform_c(lod[g], fk[i], Fr);
+                  const R s2 = fma_uniform_c(P, P, readlane_any(qv, i * 8 + g));
+                  hot |= __builtin_amdgcn_ballot_w64(s2 > smx2[g]);
+                }
+              }
             }
           }
           hotm |= (hot != 0 ? 1u : 0u) << i;
@@ -2542,22 +2574,26 @@ int plan_batch(const Problem* const* prs, const DevWork* ws, int n, const double
   // the skip test (FP64) when a problem's blocks qualify for it; the SKIP
   // kernel tests every half row of the others
   P.skip = false;
-  if (P.lodf_kind == kLodfF64)
-    for (int i = 0; i < n; ++i)
-      P.skip = P.skip || (prs[i]->tile.lt >= kSkipMinTiles && prs[i]->tile.lt <= 64 / kBatchTcw);
+  for (int i = 0; i < n; ++i)
+    P.skip = P.skip || (prs[i]->dp.lmaxh != nullptr && prs[i]->tile.lt >= kSkipMinTiles &&
+                        prs[i]->tile.lt <= 64 / kBatchTcw);
   hipError_t e;
-  if (P.lodf_kind == kLodfF64 && P.skip)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, true>,
-                                                     kBatchWl * 64, lds);
-  else if (P.lodf_kind == kLodfF64)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, false>,
-                                                     kBatchWl * 64, lds);
+  if (P.lodf_kind == kLodfF64)
+    e = P.skip ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, true>,
+                                                              kBatchWl * 64, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<double, false>,
+                                                              kBatchWl * 64, lds);
   else if (P.lodf_kind == kLodfF32)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<float, false>,
-                                                     kBatchWl * 64, lds);
+    e = P.skip ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<float, true>,
+                                                              kBatchWl * 64, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<float, false>,
+                                                              kBatchWl * 64, lds);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<uint16_t, false>,
-                                                     kBatchWl * 64, lds);
+    e = P.skip
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<uint16_t, true>,
+                                                           kBatchWl * 64, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ctg_pm_b<uint16_t, false>,
+                                                           kBatchWl * 64, lds);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   P.pm_grid = std::max(1, std::min(P.nblk[1], ncu * per_cu));
   *plan = P;
@@ -2578,8 +2614,13 @@ int launch_eval_batch(const BatchPlan& P, void* d_buf, void* stream) {
       hipLaunchKernelGGL((k_ctg_pm_b<double, true>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
     else if (P.lodf_kind == kLodfF64)
       hipLaunchKernelGGL((k_ctg_pm_b<double, false>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+    else if (P.lodf_kind == kLodfF32 && P.skip)
+      hipLaunchKernelGGL((k_ctg_pm_b<float, true>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
     else if (P.lodf_kind == kLodfF32)
       hipLaunchKernelGGL((k_ctg_pm_b<float, false>), g, blk, lds, s, args, tab(1), P.nblk[1], ctr);
+    else if (P.skip)
+      hipLaunchKernelGGL((k_ctg_pm_b<uint16_t, true>), g, blk, lds, s, args, tab(1), P.nblk[1],
+                         ctr);
     else
       hipLaunchKernelGGL((k_ctg_pm_b<uint16_t, false>), g, blk, lds, s, args, tab(1), P.nblk[1],
                          ctr);

@@ -320,7 +320,7 @@ def test_skip_test_is_bitwise_exact(qg):
     default problem and one built with QG_FLAG_CTG_NO_SKIP give bitwise the
     same terms and gradient under tiles that take the skip (4 to 64 / TCW
     branch tiles per block, one or two masks a wavefront), and both match the
-    oracle."""
+    oracle; with FP32 or BF16 factors the skip is likewise bitwise exact."""
     c = case("c3")
     x = _solved_point(qg, c, 1500)
     mdl = oracle_model(c)
@@ -362,6 +362,18 @@ def test_skip_test_is_bitwise_exact(qg):
         assert np.array_equal(t0, t1) and np.array_equal(g0, g1), tile
         assert_terms_close(qg, t0, tr)
         assert_grad_close(c, g0, gr)
+    # FP32 and BF16 factors (FP32 arithmetic, the exact test in FP32): the
+    # same bitwise agreement with and without the skip test
+    for prec in (qg.QG_FLAG_CTG_FP32, qg.QG_FLAG_CTG_BF16):
+        for tile in ("s4x4x8", "s4x2x16"):
+            got = []
+            for flags in (prec, prec | qg.QG_FLAG_CTG_NO_SKIP):
+                prob = qg.Problem(c, flags=flags)
+                prob.set_tile(tile)
+                got.append(gpu_eval(qg, prob, x, 1e-4, 1.0, 1.0))
+                prob.close()
+            (t0, g0), (t1, g1) = got
+            assert np.array_equal(t0, t1) and np.array_equal(g0, g1), (prec, tile)
 
 
 def test_ctg_split_tile_arguments_rejected(qg):
