@@ -93,13 +93,15 @@ enum { QG_CTG_ALL_NONBRIDGE = 0, QG_CTG_LIST = 1 };
  * accumulates them); the sum goes into the QG_T_CTG_MEAN slot and
  * QG_T_CTG_MAX is 0. */
 #define QG_FLAG_CTG_SUM 0x8u
-/* Bound-based skip of the FP64 contingency map-reduce.  Default: with FP64
- * outage factors, every contingency scored and blocks of 4 to 64 / (periods
- * per wavefront) branch tiles, a half row (4 branches, one period, 64
- * contingencies) is passed over when |F_tl| + max|LODF_lk| max|F_tk| proves
- * every post-outage flow within its test radius (with margins that cover the
- * rounding), so the results are bitwise those of testing every element.
- * With this flag every element is tested (a reference for that claim). */
+/* Bound-based skip in the contingency map-reduce.  Default: with every
+ * contingency scored and blocks of 4 to 64 / (periods per wavefront) branch
+ * tiles, a half row (4 branches, one period, 64 contingencies) is passed
+ * over when |F_tl| + max|LODF_lk| max|F_tk| proves every post-outage flow
+ * within its test radius, the factors' maximum taken as stored (FP64, FP32
+ * or BF16) and with margins that cover the rounding of the exact test of
+ * that precision, so the results are bitwise those of testing every
+ * element.  With this flag every element is tested (a reference for that
+ * claim). */
 #define QG_FLAG_CTG_NO_SKIP 0x10u
 
 /* Grid description: host arrays, all FP64 per unit (100 MVA base) unless

@@ -572,6 +572,16 @@ __device__ __forceinline__ void mfma_slab_dispatch(int mtiles, ALoad aload, cons
 // ---------------------------------------------------------------------------
 // K1: branch forward, device blocks, injection blocks
 
+// Consecutive block indices go to the eight XCDs in turn.  xcd_group(p, n)
+// renumbers block p of n so that the blocks of one XCD take one contiguous
+// range of the logical order (the first n % 8 ranges one block longer): the
+// consecutive branches of a period then store their bus-sorted endpoint
+// slots through one L2, which merges the scattered stores into whole lines.
+__device__ __forceinline__ int xcd_group(int p, int n) {
+  const int q = n >> 3, rem = n & 7, x = p & 7, i = p >> 3;
+  return x * q + min(x, rem) + i;
+}
+
 __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk, double* lds) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
@@ -795,7 +805,14 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
   const DevWork& w = a.w;
   const int T = p.T, G = p.G, Lp = p.Lp, Kp = p.Kp, N = p.N;
   const int mtiles = p.Tp / 16;
-  const int slab = blk / mtiles, r0 = (blk - slab * mtiles) * 16;
+  // consecutive blocks go to the eight XCDs in turn: the period tiles of a
+  // slab take block indices eight apart, so they run on one XCD and its L2
+  // fetches the slab's ISF columns once (the last group of fewer than eight
+  // slabs spreads them over its own slabs' count)
+  const int nsl = Lp / 16, grp = 8 * mtiles;
+  const int q = blk / grp, r = blk - q * grp;
+  const int ns = min(8, nsl - 8 * q);
+  const int slab = 8 * q + r % ns, r0 = (r / ns) * 16;
   const double* xP = a.x + 2 * (size_t)T * N;
   const int n0 = slab * 16;
   double* F = w.F;
@@ -838,7 +855,7 @@ __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* s
   if (b < a.p.T)
     period_block(a, sp, b, smem);
   else if (b < a.nb_br + a.p.T)
-    branch_forward(a, sp, b - a.p.T, smem);
+    branch_forward(a, sp, xcd_group(b - a.p.T, a.nb_br), smem);
   else
     flow_slab(a, b - a.nb_br - a.p.T, smem);
 }
@@ -1660,10 +1677,14 @@ __device__ __forceinline__ void ctg_asm_body(const EvalArgs& a, int b, int nbloc
     const int64_t s1 = min(a.w.step[0] + 1, (int64_t)kSchedCap - 1);
     a.w.snext[threadIdx.x] = a.w.sched[s1 * kSchedStride + threadIdx.x];
   }
-  if (b < nasm)
-    ctg_assemble<SPARSE>(a, b / a.nLc, b % a.nLc, smem);
-  else
+  if (b < nasm) {
+    // XCD-grouped: the blocks of consecutive periods store the transposed
+    // flow adjoints gfT[l][t] of the same branches through one L2
+    const int g = xcd_group(b, nasm);
+    ctg_assemble<SPARSE>(a, g / a.nLc, g % a.nLc, smem);
+  } else {
     bus_balance(a, b - nasm, smem);
+  }
 }
 
 template <bool SPARSE>
@@ -1738,7 +1759,7 @@ __device__ __forceinline__ void adjoint_body(const EvalArgs& a, int bx, double* 
   }
   const int b = bx - nslab * a.nsplit;
   if (b < a.nb_br) {
-    branch_reverse(a, b);
+    branch_reverse(a, xcd_group(b, a.nb_br));
     return;
   }
   // the worst outage's ISF row of each period (generator columns), for the
