@@ -1739,7 +1739,10 @@ __device__ __forceinline__ void adjoint_body(const EvalArgs& a, int bx, double* 
   const DevProblem& p = a.p;
   const int nslab = p.G16 / 16;
   if (bx < nslab * a.nsplit) {
-    const int slab = bx % nslab, sp = bx / nslab;
+    // XCD-grouped: the slabs of one slice, which read the same rows of the
+    // flow adjoints, mostly share an L2
+    const int g = xcd_group(bx, nslab * a.nsplit);
+    const int slab = g % nslab, sp = g / nslab;
     const int n0 = slab * 16;
     const int steps = p.Lp / 4;
     const int per = (steps + a.nsplit - 1) / a.nsplit;
