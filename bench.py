@@ -282,7 +282,10 @@ def main():
     torch.cuda.synchronize()
     kms_step = {k: float(ms) for k, ms in zip(qg.KERNEL_NAMES, list(rep_p.kernel_ms))}
     work = kernel_work(case, prob.dims)
-    dom = max(kms, key=lambda k: kms[k])
+    # the dominant kernel: the largest share of a step (the in-step durations;
+    # a short kernel's back-to-back mean varies with the clock more than the
+    # order of the in-step durations does); its rate over the back-to-back mean
+    dom = max(kms_step, key=lambda k: kms_step[k])
     bound, amount, unit = work[dom]
     sec = kms[dom] * 1e-3
     if bound == "hbm":
