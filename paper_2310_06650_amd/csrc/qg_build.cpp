@@ -360,8 +360,10 @@ qg_status plan_problem(const qg_grid_desc* d, const qg_build_opts* o, Problem* p
   int o2 = 0;
   to.br = o2; o2 += p->nb_br;
   to.ang = o2; o2 += p->nb_br;
-  to.dev = o2; o2 += T;
-  to.pen = o2; o2 += T;
+  // device terms: one partial per period and slice of kBlock generators
+  const int ndev = T * ((p->G + kBlock - 1) / kBlock);
+  to.dev = o2; o2 += ndev;
+  to.pen = o2; o2 += ndev;
   to.rsv = o2; o2 += T;
   to.bal = o2; o2 += p->nb_bus;
   to.cmax = o2; o2 += T;

@@ -2,8 +2,6 @@
 //
 // Stage map (one launch each, in stream order):
 //   k_forward       per-(t, branch) AC flows and penalties          (Section II-B Ex. 1, 4; II-G)
-//                   + one block per period: device terms, reserve     (Ex. 2, 3; eq. (nlp_updated))
-//                     shortfall
 //                   + base-case DC flows on FP64 MFMA:                 (eqs. (Yb_solve)-(p_flow))
 //                     F_t = ISF[:, gen] p_t - ISF load_t - mean_t ISF 1 (uniform slack)
 //   k_ctg_main      per-(t, l, k) outage flows F_l + LODF_lk F_k, their (eqs. (rank_correct),
@@ -13,6 +11,8 @@
 //   k_ctg_asm       per-(t, l) dL/dF and dL/dqmax2 (mean + worst-contingency weights)
 //                   + per-(t, bus) power balance from bus-sorted endpoint flows
 //                     (LDS-staged segmented sums)                      (Ex. 4)
+//                   + one block per period: device terms, reserve     (Ex. 2, 3; eq. (nlp_updated))
+//                     shortfall
 //   k_adjoint       dL/dp_tj (DC part) = sum_l dL/dF_tl (ISF[l][bus(j)] - rowsum_l/N)
 //                     on FP64 MFMA, split over the branch dimension      (eqs. (2nd_lin_sys), (correction))
 //                   + per-(t, branch) reverse of the AC flows into bus-sorted endpoint slots
@@ -665,9 +665,12 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
 // 2-3), the penalised device constraints of eq. (nlp_updated) and their
 // partials.  The next period's terms that depend on this period's p and u
 // are included, so each thread writes only its own partials.  The block also
-// sums the period's reserve (for the shortfall penalty) and zeroes the
-// padding read later.
-__device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, double* lds) {
+// sums the period's reserve (for the shortfall penalty).  Only the final
+// kernel reads what it writes, so it runs in k_ctg_asm's launch, beside the
+// contingency reductions: in the forward kernel its registers (the most of
+// any block there) held that kernel to four wavefronts per SIMD.
+__device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, int sl,
+                             double* lds) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int T = p.T, N = p.N, G = p.G, M = p.M;
@@ -680,8 +683,9 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
   const double dtt = p.dt[t];
   const double kpen = sp.rho_s * p.rho * sp.beta * dtt;
   const double eps = sp.eps;
-  double acc[3] = {0.0, 0.0, 0.0};  // dev, pen, sum r
-  for (int j = tid; j < G; j += kBlock) {
+  double acc[2] = {0.0, 0.0};  // dev, pen
+  const int j = sl * kBlock + tid;
+  if (j < G) {
     const size_t e = (size_t)t * G + j;
     // every load of the generator first, so that their latencies overlap
     const double pj = xP[e], qj = xQ[e], rj = xR[e], uj = xU[e];
@@ -767,18 +771,34 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
     w.gdev[1 * TG + e] = gq;
     w.gdev[2 * TG + e] = gr;
     w.gdev[3 * TG + e] = gu;
-    acc[0] += dev;
-    acc[1] += kpen * pen;
-    acc[2] += rj;
+    acc[0] = dev;
+    acc[1] = kpen * pen;
   }
-  block_sum<3>(acc, lds);
-  const double short_ = p.rsv_req[t] - acc[2];
-  const double krs = dtt * p.c_rsv * sp.beta;
+  block_sum<2>(acc, lds);
   if (tid == 0) {
-    w.tpart[a.toff.dev + t] = acc[0];
-    w.tpart[a.toff.pen + t] = acc[1];
-    w.tpart[a.toff.rsv + t] = krs * soft_relu(short_, eps);
-    w.drs[t] = krs * soft_relu_d(short_, eps);
+    const int q = t * ((G + kBlock - 1) / kBlock) + sl;
+    w.tpart[a.toff.dev + q] = acc[0];
+    w.tpart[a.toff.pen + q] = acc[1];
+  }
+}
+
+// Period t's reserve shortfall penalty and its derivative (eq.
+// (nlp_updated)), which every generator's reserve partial needs; and the
+// padding of period t that the map-reduce reads: branches past L pass
+// every test (q2 = 0, radius -1), outages past K have no flow.
+__device__ void pad_block(const EvalArgs& a, const StepParams& sp, int t, double* lds) {
+  const DevProblem& p = a.p;
+  const DevWork& w = a.w;
+  const int tid = threadIdx.x, T = p.T, G = p.G;
+  const double* xR = a.x + 2 * (size_t)T * p.N + 2 * (size_t)T * G;
+  double acc[1] = {0.0};
+  for (int j = tid; j < G; j += kBlock) acc[0] += xR[(size_t)t * G + j];
+  block_sum<1>(acc, lds);
+  if (tid == 0) {
+    const double short_ = p.rsv_req[t] - acc[0];
+    const double krs = p.dt[t] * p.c_rsv * sp.beta;
+    w.tpart[a.toff.rsv + t] = krs * soft_relu(short_, sp.eps);
+    w.drs[t] = krs * soft_relu_d(short_, sp.eps);
   }
   for (int l = p.L + tid; l < p.Lp; l += kBlock) {
     w.q2[(size_t)t * p.Lp + l] = 0.0;
@@ -792,6 +812,10 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, dou
 // keeps four wavefronts x up to 4 row tiles x 256 partial results.
 constexpr int kSlabLds = 4 * 4 * 256;
 static_assert(kSlabLds >= 2 * kSegChunk + 8 * kBlock, "LDS carve");
+// LDS of the forward kernel: the flow slab's single row tile (its block sums
+// need 32 doubles), so that LDS does not limit its blocks per CU.
+constexpr int kFwdLds = 4 * 1 * 256;
+static_assert(kFwdLds >= 2 * 16, "LDS carve");
 
 // Base-case DC flows of 16 branches for 16 periods, on FP64 MFMA, with the
 // uniform slack folded into the operand: F[t][l] = sum_j p_tj (ISF[l][bus(j)]
@@ -837,9 +861,8 @@ __device__ void flow_slab(const EvalArgs& a, int blk, double* smem) {
   mfma_slab<1, 8>(aload, p.isf_gT, Lp, 0, p.G4, n0, smem, epi);
 }
 
-// Blocks [0, T): one period each (the longest chains of the kernel, so they
-// are dispatched first); [T, T + nb_br): branch forward; then (Lp / 16) x
-// (Tp / 16) flow slabs.
+// Blocks [0, T): the reserve shortfall and the padding of one period each;
+// [T, T + nb_br): branch forward; then (Lp / 16) x (Tp / 16) flow slabs.
 __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* smem) {
   StepParams sp;
   resolve_params(a, sp);
@@ -853,7 +876,7 @@ __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* s
     pb[PB_BC2] = sp.bc2;
   }
   if (b < a.p.T)
-    period_block(a, sp, b, smem);
+    pad_block(a, sp, b, smem);
   else if (b < a.nb_br + a.p.T)
     branch_forward(a, sp, xcd_group(b - a.p.T, a.nb_br), smem);
   else
@@ -861,7 +884,7 @@ __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* s
 }
 
 __global__ __launch_bounds__(kBlock) void k_forward(EvalArgs a) {
-  __shared__ double smem[kSlabLds];
+  __shared__ double smem[kFwdLds];
   forward_body(a, blockIdx.x, smem);
 }
 
@@ -1664,12 +1687,16 @@ __device__ void ctg_assemble(const EvalArgs& a, int t, int lc, double* red) {
   if (tid == 0) w.smaxp[(size_t)t * a.nLc + lc] = sacc[0];
 }
 
-// Blocks [0, nLc T): flow adjoints of (period, 256-branch chunk); then the
-// nb_bus power-balance blocks, which only need the forward flows.
+// Blocks [0, T nsl): the device terms of one period and one slice of 256
+// generators each (period_block, with the step's parameters as the forward
+// kernel resolved them; nsl slices per period); then nLc T blocks of flow
+// adjoints of (period, 256-branch chunk); then the nb_bus power-balance
+// blocks, which only need the forward flows.
 template <bool SPARSE>
 __device__ __forceinline__ void ctg_asm_body(const EvalArgs& a, int b, int nblocks,
                                              double* smem) {
-  const int nasm = a.nLc * a.p.T;
+  const int T = a.p.T, nasm = a.nLc * T;
+  const int nsl = (a.p.G + kBlock - 1) / kBlock, nper = T * nsl;
   // scheduled steps: the next step's schedule row (the counter is advanced
   // by k_final, after this kernel), clamped to the table; a new table comes
   // with k_set_step, which copies its own row
@@ -1677,13 +1704,19 @@ __device__ __forceinline__ void ctg_asm_body(const EvalArgs& a, int b, int nbloc
     const int64_t s1 = min(a.w.step[0] + 1, (int64_t)kSchedCap - 1);
     a.w.snext[threadIdx.x] = a.w.sched[s1 * kSchedStride + threadIdx.x];
   }
-  if (b < nasm) {
+  if (b < nper) {
+    StepParams sp{};
+    sp.eps = a.w.params[PB_EPS];
+    sp.beta = a.w.params[PB_BETA];
+    sp.rho_s = a.w.params[PB_RHO];
+    period_block(a, sp, b / nsl, b % nsl, smem);
+  } else if (b < nper + nasm) {
     // XCD-grouped: the blocks of consecutive periods store the transposed
     // flow adjoints gfT[l][t] of the same branches through one L2
-    const int g = xcd_group(b, nasm);
+    const int g = xcd_group(b - nper, nasm);
     ctg_assemble<SPARSE>(a, g / a.nLc, g % a.nLc, smem);
   } else {
-    bus_balance(a, b - nasm, smem);
+    bus_balance(a, b - nper - nasm, smem);
   }
 }
 
@@ -1903,11 +1936,12 @@ __device__ __forceinline__ void final_body(const EvalArgs& a, int bx, double* sm
   // thread's loads are in flight together)
   const TermOffsets& to = a.toff;
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int nq = max(max(a.nb_br, T), a.nb_bus);
+  const int ndev = T * ((G + kBlock - 1) / kBlock);  // device-term slices
+  const int nq = max(max(a.nb_br, ndev), a.nb_bus);
   for (int q = tid; q < nq; q += kBlock) {
-    const bool ib = q < a.nb_br, it = q < T, iu = q < a.nb_bus;
+    const bool ib = q < a.nb_br, it = q < T, iu = q < a.nb_bus, id = q < ndev;
     const double br = ib ? w.tpart[to.br + q] : 0.0, an = ib ? w.tpart[to.ang + q] : 0.0;
-    const double dv = it ? w.tpart[to.dev + q] : 0.0, pn = it ? w.tpart[to.pen + q] : 0.0;
+    const double dv = id ? w.tpart[to.dev + q] : 0.0, pn = id ? w.tpart[to.pen + q] : 0.0;
     const double rs = it ? w.tpart[to.rsv + q] : 0.0, cx = it ? w.tpart[to.cmax + q] : 0.0;
     const double cm = it ? w.tpart[to.cmean + q] : 0.0, bl = iu ? w.tpart[to.bal + q] : 0.0;
     v[0] += dv; v[1] += bl; v[2] += br; v[3] += an;
@@ -2087,6 +2121,12 @@ static EvalArgs make_args(const Problem* pr, const DevWork& w, const double* x, 
   return a;
 }
 
+// Blocks of k_ctg_asm: the device-term slices, the flow-adjoint chunks and
+// the bus-balance blocks.
+static int asm_blocks(const Problem* pr) {
+  return pr->T * ((pr->G + kBlock - 1) / kBlock) + pr->nLc * pr->T + pr->nb_bus;
+}
+
 // One kernel of the step, in stream order 0..kStages-1.
 static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStream_t s) {
   switch (stage) {
@@ -2115,10 +2155,10 @@ static void launch_stage(const Problem* pr, const EvalArgs& a, int stage, hipStr
       break;
     case 3:
       if (a.sparse)
-        hipLaunchKernelGGL(k_ctg_asm<true>, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0,
+        hipLaunchKernelGGL(k_ctg_asm<true>, dim3(asm_blocks(pr)), dim3(kBlock), 0,
                            s, a);
       else
-        hipLaunchKernelGGL(k_ctg_asm<false>, dim3(pr->nLc * pr->T + pr->nb_bus), dim3(kBlock), 0,
+        hipLaunchKernelGGL(k_ctg_asm<false>, dim3(asm_blocks(pr)), dim3(kBlock), 0,
                            s, a);
       break;
     case 4:
@@ -2164,7 +2204,7 @@ __device__ __forceinline__ void batch_entry(const uint32_t* __restrict__ tab, ui
 
 __global__ __launch_bounds__(kBlock) void k_forward_b(const EvalArgs* __restrict__ args,
                                                       const uint32_t* __restrict__ tab, int* ctr) {
-  __shared__ double smem[kSlabLds];
+  __shared__ double smem[kFwdLds];
   // the work counter of this step's map-reduce (the previous step's has
   // finished: the launches are ordered)
   if (blockIdx.x == 0 && threadIdx.x == 0) *ctr = 0;
@@ -2489,7 +2529,8 @@ __global__ __launch_bounds__(kBlock) void k_ctg_asm_b(const EvalArgs* __restrict
   int s, b;
   batch_entry(tab, blockIdx.x, s, b);
   const EvalArgs& a = args[s];
-  ctg_asm_body<true>(a, b, a.nLc * a.p.T + a.nb_bus, smem);
+  ctg_asm_body<true>(a, b, a.p.T * ((a.p.G + kBlock - 1) / kBlock) + a.nLc * a.p.T + a.nb_bus,
+                     smem);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adjoint_b(const EvalArgs* __restrict__ args,
@@ -2514,7 +2555,7 @@ static void stage_blocks(const Problem* pr, const EvalArgs& a, int out[kStages])
   out[0] = pr->nb_br + pr->T + pr->Lp / 16 * (pr->Tp / 16);
   out[1] = pr->K > 0 ? pr->nLb * a.nKb * ((pr->T + span - 1) / span) : 0;
   out[2] = pr->K > 0 ? a.nKc * pr->T : 0;
-  out[3] = pr->nLc * pr->T + pr->nb_bus;
+  out[3] = asm_blocks(pr);
   out[4] = pr->G16 / 16 * pr->nsplit + pr->nb_br + (pr->T * pr->G16 + kBlock - 1) / kBlock;
   out[5] = pr->nb_bus + pr->nb_gen + 1;
 }
