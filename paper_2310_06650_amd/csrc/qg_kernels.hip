@@ -660,13 +660,14 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
   }
 }
 
-// One block per period t, one thread per generator (looping when G > 256):
-// block-bid cost, no-load, start-up/shut-down and reserve costs (Examples
-// 2-3), the penalised device constraints of eq. (nlp_updated) and their
-// partials.  The next period's terms that depend on this period's p and u
-// are included, so each thread writes only its own partials.  The block also
-// sums the period's reserve (for the shortfall penalty).  Only the final
-// kernel reads what it writes, so it runs in k_ctg_asm's launch, beside the
+// One block per period t and slice sl of 256 generators, one thread per
+// generator: block-bid cost, no-load, start-up/shut-down and reserve costs
+// (Examples 2-3), the penalised device constraints of eq. (nlp_updated) and
+// their partials, and the slice's sums of the cost and penalty terms.  The
+// next period's terms that depend on this period's p and u are included, so
+// each thread writes only its own partials; the reserve shortfall, which
+// needs the whole period's reserve, is pad_block's.  Only the final kernel
+// reads what it writes, so it runs in k_ctg_asm's launch, beside the
 // contingency reductions: in the forward kernel its registers (the most of
 // any block there) held that kernel to four wavefronts per SIMD.
 __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, int sl,
