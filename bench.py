@@ -106,10 +106,11 @@ def kernel_source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def stored_traffic(kernel, config):
+def stored_traffic(kernel, config, tile):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
-    (profiles/<kernel>_<config>_traffic.md), or None when there is none or the
-    kernel source changed since the counters were taken."""
+    (profiles/<kernel>_<config>_traffic.md), or None when there is none, the
+    kernel source changed since the counters were taken or they were taken
+    with another map-reduce tile."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -120,6 +121,8 @@ def stored_traffic(kernel, config):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    if vals.get("ctg_tile") != tile:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -301,7 +304,7 @@ def main():
     # the map-reduce stage runs k_ctg_pm under a period-split tile
     kname = "k_ctg_pm" if (dom == "k_ctg_main" and prob.dims["ctg_split"]) else dom
     roof = dict(bound=bound, kernel=kname, achieved=achieved, peak=peak, unit=runit,
-                frac=achieved / peak, traffic=stored_traffic(kname, args.config),
+                frac=achieved / peak, traffic=stored_traffic(kname, args.config, prob.tile()),
                 per_launch=f"{amount:.4g} {unit} algorithmic, mean {kms[dom] * 1e3:.2f} us/launch")
     out = dict(metric=METRIC, value=steps_per_s, unit="steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, repeats=args.repeats, ms_per_step=1e3 * el / args.steps,
