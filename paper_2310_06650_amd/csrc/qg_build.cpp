@@ -225,13 +225,14 @@ int default_ctg_lt(const Problem& p, const CtgTile& t) {
 
 CtgTile default_ctg_tile(const Problem& p) {
   // period-split blocks: four wavefronts of two periods below 32 periods,
-  // two wavefronts of four from there; branch tiles per block by the rule of
+  // one wavefront of four from there; branch tiles per block by the rule of
   // default_ctg_lt.  Measured as whole graph-replayed steps against the best
   // branch-stacked tile: 4.8 % faster at 18 periods (28.8k against 27.5k
-  // steps/s), 1.6x at 48; at 48 periods two wavefronts of four periods are
-  // 2.9 % faster than four (10.0k against 9.7k steps/s, 2000 buses), at 18
-  // four of two are the fastest.
-  CtgTile t{8, p.T >= 32 ? 2 : 4, p.T >= 32 ? 4 : 2, 2};
+  // steps/s), 1.6x at 48; at 48 periods (2000 buses) blocks of one
+  // wavefront of four periods run 10.15k steps/s against 9.99k for two
+  // and 9.72k for four; at 18 periods four wavefronts of two are within
+  // 1 % of the best.
+  CtgTile t{8, p.T >= 32 ? 1 : 4, p.T >= 32 ? 4 : 2, 2};
   t.split = 1;
   t.lt = default_ctg_lt(p, t);
   return t;

@@ -242,15 +242,15 @@ def test_ctg_split_tile_reduced_precision_matches_stacked(qg, flag):
 
 
 def test_ctg_split_tiles_c3_against_oracle(qg):
-    """The 2,000-bus, 48-period grid: the default split tile (two wavefronts
-    of four periods, six period chunks) and one chunk of all 48 periods (each
-    factor read once)."""
+    """The 2,000-bus, 48-period grid: the default split tile (one wavefront
+    of four periods, twelve period chunks) and one chunk of all 48 periods
+    (each factor read once)."""
     c = case("c3")
     x = synth.random_point(c, 7, spread=0.3)
     tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 1.0, 1.0)
     for tile in (None, (8, 6, 8)):
         prob = qg.Problem(c)
-        assert prob.tile() == f"s2x4x{prob.dims['ctg_lt']}"   # four periods a wavefront from 32
+        assert prob.tile() == f"s1x4x{prob.dims['ctg_lt']}"   # four periods a wavefront from 32
         if tile:
             prob.set_ctg_tile_split(*tile)
         t, g = gpu_eval(qg, prob, x, 1e-2, 1.0, 1.0)
