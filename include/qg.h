@@ -371,8 +371,9 @@ qg_status qg_problem_dims(const qg_problem* prob, int32_t* dims, int32_t capacit
  * wavefront (8, 16 or 32), wl wavefronts per block (1, 2, 4 or 8) stacked
  * along the branches with bl*wl >= 16, and tc periods per block (0: a default
  * from the problem size; at most 8, and at most T).  A new problem starts
- * with the period-split tile of qg_set_ctg_tile_split (wl 4 and tcw 2 below
- * 32 periods, wl 1 and tcw 4 from there, default lt).  The results do not depend on the
+ * with the period-split tile of qg_set_ctg_tile_split (below 32 periods tcw
+ * 2 and wl 4, 3 or 2, whichever pads the last period chunk least, ties to
+ * the larger; from 32 periods wl 1 and tcw 4; default lt).  The results do not depend on the
  * tile except through the order of floating-point sums.  A step graph cached
  * by qg_solve is re-captured after a change.  Errors: ARG.
  */

@@ -224,15 +224,28 @@ int default_ctg_lt(const Problem& p, const CtgTile& t) {
 }
 
 CtgTile default_ctg_tile(const Problem& p) {
-  // period-split blocks: four wavefronts of two periods below 32 periods,
-  // one wavefront of four from there; branch tiles per block by the rule of
-  // default_ctg_lt.  Measured as whole graph-replayed steps against the best
-  // branch-stacked tile: 4.8 % faster at 18 periods (28.8k against 27.5k
-  // steps/s), 1.6x at 48; at 48 periods (2000 buses) blocks of one
-  // wavefront of four periods run 10.15k steps/s against 9.99k for two
-  // and 9.72k for four; at 18 periods four wavefronts of two are within
-  // 1 % of the best.
-  CtgTile t{8, p.T >= 32 ? 1 : 4, p.T >= 32 ? 4 : 2, 2};
+  // period-split blocks: below 32 periods four, three or two wavefronts of
+  // two periods, whichever leaves the fewest padded periods in the last
+  // period chunk (ties to more wavefronts); from 32 periods one wavefront
+  // of four.  Branch tiles per block by the rule of default_ctg_lt.
+  // Measured as whole graph-replayed steps: against the best branch-stacked
+  // tile 4.8 % faster at 18 periods, 1.6x at 48; at 18 periods (617 buses)
+  // three wavefronts run 31.1k steps/s against 30.8k for four (whose last
+  // chunk holds 2 of 8 periods); at 48 periods (2000 buses) one wavefront
+  // runs 10.15k against 9.99k for two and 9.72k for four.
+  int wl = 1, tc = 4;
+  if (p.T < 32) {
+    tc = 2;
+    int fewest = 1 << 30;
+    for (int w = 4; w >= 2; --w) {
+      const int span = w * tc, pad = (p.T + span - 1) / span * span - p.T;
+      if (pad < fewest) {
+        fewest = pad;
+        wl = w;
+      }
+    }
+  }
+  CtgTile t{8, wl, tc, 2};
   t.split = 1;
   t.lt = default_ctg_lt(p, t);
   return t;

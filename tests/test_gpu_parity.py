@@ -211,7 +211,7 @@ def test_ctg_split_tile_invariance(qg, wl, tcw, lt):
     c = case("c2")
     prob = qg.Problem(c)
     assert prob.dims["ctg_split"] == 1          # the default form
-    assert prob.tile() == f"s4x2x{prob.dims['ctg_lt']}"
+    assert prob.tile() == f"s3x2x{prob.dims['ctg_lt']}"      # 18 periods: 3 chunks of 6
     x = synth.random_point(c, 10, spread=0.3)
     prob.set_ctg_tile(8, 8, 4, lt=1)
     assert prob.dims["ctg_split"] == 0
