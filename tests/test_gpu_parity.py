@@ -583,6 +583,24 @@ def test_ragged_sizes(qg, T):
     assert_grad_close(c, g, gr)
 
 
+@pytest.mark.parametrize("T,wl,tcw", [(1, 2, 2), (4, 2, 2), (12, 3, 2), (20, 2, 2), (24, 4, 2),
+                                      (31, 4, 2), (32, 1, 4), (48, 1, 4)])
+def test_default_split_tile_by_period_count(qg, T, wl, tcw):
+    """The default map-reduce tile: below 32 periods four, three or two
+    wavefronts of two periods, whichever pads the last period chunk least
+    (ties to more wavefronts); from 32 periods one wavefront of four.  The
+    results at that tile agree with the oracle."""
+    c = synth.make_case(seed=60 + T, n_bus=37, n_branch=71, n_gen=9, n_period=T, n_ctg=None)
+    prob = qg.Problem(c)
+    d = prob.dims
+    assert d["ctg_split"] == 1 and (d["ctg_wl"], d["ctg_tc"]) == (wl, tcw)
+    x = synth.random_point(c, T + 1)
+    t, g = gpu_eval(qg, prob, x, 5e-2, 0.9, 0.8)
+    tr, gr = ob.evaluate(oracle_model(c), x, 5e-2, 0.9, 0.8)
+    assert_terms_close(qg, t, tr)
+    assert_grad_close(c, g, gr)
+
+
 def test_misaligned_buffer_rejected(qg):
     import torch
     c = case("c1")
