@@ -666,8 +666,8 @@ __device__ void branch_forward(const EvalArgs& a, const StepParams& sp, int blk,
 // their partials, and the slice's sums of the cost and penalty terms.  The
 // next period's terms that depend on this period's p and u are included, so
 // each thread writes only its own partials; the reserve shortfall, which
-// needs the whole period's reserve, is pad_block's.  Only the final kernel
-// reads what it writes, so it runs in k_ctg_asm's launch, beside the
+// needs the whole period's reserve, is reserve_pad_block's.  Only the final
+// kernel reads what it writes, so it runs in k_ctg_asm's launch, beside the
 // contingency reductions: in the forward kernel its registers (the most of
 // any block there) held that kernel to four wavefronts per SIMD.
 __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, int sl,
@@ -787,7 +787,7 @@ __device__ void period_block(const EvalArgs& a, const StepParams& sp, int t, int
 // (nlp_updated)), which every generator's reserve partial needs; and the
 // padding of period t that the map-reduce reads: branches past L pass
 // every test (q2 = 0, radius -1), outages past K have no flow.
-__device__ void pad_block(const EvalArgs& a, const StepParams& sp, int t, double* lds) {
+__device__ void reserve_pad_block(const EvalArgs& a, const StepParams& sp, int t, double* lds) {
   const DevProblem& p = a.p;
   const DevWork& w = a.w;
   const int tid = threadIdx.x, T = p.T, G = p.G;
@@ -877,7 +877,7 @@ __device__ __forceinline__ void forward_body(const EvalArgs& a, int b, double* s
     pb[PB_BC2] = sp.bc2;
   }
   if (b < a.p.T)
-    pad_block(a, sp, b, smem);
+    reserve_pad_block(a, sp, b, smem);
   else if (b < a.nb_br + a.p.T)
     branch_forward(a, sp, xcd_group(b - a.p.T, a.nb_br), smem);
   else
