@@ -22,8 +22,8 @@ import os
 from . import qg
 
 # text forms; a missing lt: the library's default for the rest of the tile
-CANDIDATES = ["s4x2", "s4x4", "s2x2", "s8x2", "s4x3", "s4x6", "s8x6", "s4x4x16", "s4x2x4",
-              "s2x4x8", "s3x4x8", "s4x2x16",
+CANDIDATES = ["s4x2", "s4x4", "s2x2", "s3x2", "s8x2", "s4x3", "s4x6", "s8x6", "s4x4x16",
+              "s4x2x4", "s1x4", "s1x4x8", "s1x4x12", "s2x4x8", "s3x4x8", "s4x2x16",
               "8x8x4", "8x4x4", "8x8x7", "16x4x4", "8x8x4x1", "8x8x7x4", "8x4x8x8"]
 # the tiles a batched solve takes (4 wavefronts of 4 periods; branch tiles
 # per block free).  In a batch the map-reduce's blocks are work items of a
