@@ -706,6 +706,46 @@ def test_batched_solve_matches_single_solves(qg):
         qg.solve_batch(probs, xs, ms, vs, opts)
 
 
+@pytest.mark.parametrize("flag", ["QG_FLAG_CTG_FP32", "QG_FLAG_CTG_BF16"])
+def test_batched_reduced_precision_matches_single_solves(qg, flag):
+    """Batched steps with FP32 or BF16 outage factors (the batched
+    map-reduce's reduced-precision forms; with four branch tiles per block
+    the skip test runs in them) end where each scenario solved alone ends,
+    bit for bit."""
+    import torch
+    shapes = [(80, 12), (150, 36), (260, 20)]
+    cases = [synth.make_case(seed=4200 + i, n_bus=nb, n_branch=int(round(1.4 * nb)),
+                             n_gen=max(2, int(round(0.15 * nb))), n_period=T, n_ctg=None,
+                             tree="prufer", mesh=3.0, name=f"p{i}")
+             for i, (nb, T) in enumerate(shapes)]
+    opts = qg.solve_opts(21, [1e-3] * 6, alphaf=[1e-4] * 6, eps0=1e-1, epsf=1e-3, use_graph=1)
+    alone, probs, xs, ms, vs = [], [], [], [], []
+    for c in cases:
+        p = qg.Problem(c, flags=getattr(qg, flag))
+        assert p.K > 0
+        p.set_tile("s4x4x4")
+        x0 = synth.flat_start(c)
+        x, m, v = p.new_vector(x0), p.new_vector(), p.new_vector()
+        p.solve(x, m, v, opts)
+        torch.cuda.synchronize()
+        alone.append((x.cpu().numpy().copy(), m.cpu().numpy().copy()))
+        x.copy_(torch.from_numpy(x0).to(x.device))
+        m.zero_()
+        v.zero_()
+        probs.append(p)
+        xs.append(x)
+        ms.append(m)
+        vs.append(v)
+    reps = qg.solve_batch(probs, xs, ms, vs, opts)
+    torch.cuda.synchronize()
+    for (a, am), x, m, r in zip(alone, xs, ms, reps):
+        assert np.array_equal(a, x.cpu().numpy())
+        assert np.array_equal(am, m.cpu().numpy())
+        assert r.steps_done == 21 and np.isfinite(r.final_score)
+    for p in probs:
+        p.close()
+
+
 def test_batched_steps_match_oracle_uneven_sizes(qg):
     """Four scenarios spanning the batch range (100 to 2,000 buses, 12 to 48
     periods, every non-islanding outage) take two batched steps from seeded
