@@ -819,6 +819,25 @@ def test_autotuner_picks_a_timed_tile_and_caches_it(qg, tmp_path, monkeypatch):
     assert prob2.tile() == tile3
 
 
+def test_sum_aggregation_with_skip_test(qg):
+    """QG_FLAG_CTG_SUM under a tile that takes the skip test (eight branch
+    tiles, four periods a wavefront): agrees with the oracle and, bit for
+    bit, with testing every element."""
+    c = case("c2")
+    x = synth.random_point(c, 17, spread=0.3)
+    tr, gr = ob.evaluate(oracle_model(c), x, 1e-2, 0.9, 1.0, agg="sum")
+    out = []
+    for flags in (qg.QG_FLAG_CTG_SUM, qg.QG_FLAG_CTG_SUM | qg.QG_FLAG_CTG_NO_SKIP):
+        prob = qg.Problem(c, flags=flags)
+        prob.set_tile("s2x4x8")
+        t, g = gpu_eval(qg, prob, x, 1e-2, 0.9, 1.0)
+        assert_terms_close(qg, t, tr)
+        assert_grad_close(c, g, gr)
+        out.append((t, g))
+        prob.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 @pytest.mark.parametrize("name", ["c1", "c2"])
 def test_sum_aggregation(qg, name):
     """QG_FLAG_CTG_SUM: per-period sum over contingencies (also with a
