@@ -570,13 +570,17 @@ __device__ __forceinline__ void mfma_slab_dispatch(int mtiles, ALoad aload, cons
 }
 
 // ---------------------------------------------------------------------------
-// K1: branch forward, device blocks, injection blocks
+// K1: branch forward, reserve and padding blocks, flow slabs
 
 // Consecutive block indices go to the eight XCDs in turn.  xcd_group(p, n)
 // renumbers block p of n so that the blocks of one XCD take one contiguous
-// range of the logical order (the first n % 8 ranges one block longer): the
-// consecutive branches of a period then store their bus-sorted endpoint
-// slots through one L2, which merges the scattered stores into whole lines.
+// range of the logical order (the first n % 8 ranges one block longer), so
+// that neighbouring logical blocks share an L2: the consecutive branches of
+// a period store their bus-sorted endpoint slots through it (which merges
+// the scattered stores into whole lines), and the blocks that read one
+// operand fetch it from memory once per XCD.  Used by the branch blocks of
+// the forward and adjoint kernels, the flow-adjoint assembly and the
+// adjoint product's slabs.
 __device__ __forceinline__ int xcd_group(int p, int n) {
   const int q = n >> 3, rem = n & 7, x = p & 7, i = p >> 3;
   return x * q + min(x, rem) + i;
